@@ -1,0 +1,196 @@
+/*
+ * fht.h -- C ABI of the MI355X (gfx950) Fast Hough Transform library, libfht.so.
+ *
+ * The transform is Brady's dyadic Fast Hough Transform in the form studied by
+ * Aliev, Ershov and Nikolaev (arXiv 1811.06378): sums of an image along all
+ * dyadic linear patterns, with the paper's zero extension (section 3.1), the
+ * four angle quadrants concatenated into one full Hough image (section 3.3),
+ * the angle-range modification that shears the image inside the first
+ * iteration (section 4) and the fhtshift regrouping (section 5).
+ *
+ * Conventions.
+ *   Image I: h rows x w columns, element (x, y) at img[y * ld_img + x].
+ *   h' = 2^ceil(log2 h), w' = 2^ceil(log2 w), W = w' + h'.  Both sides are
+ *   padded with zeros to the next power of two and the image is extended by
+ *   h' zero columns (w' for the transposed image), so every quadrant has W
+ *   columns and patterns never wrap into the image (section 3.1).
+ *   D_n(s, y) is the column offset at row y of the dyadic pattern with shift s
+ *   over n rows: the top half uses shift s>>1, the bottom half uses s>>1 and
+ *   starts s - (s>>1) columns further (section 2; section 4, Fig. 6).
+ *   Quadrant 1 [315;0]:  H1[s,x] = sum_y P [y, (x + D_h'(s,y)) mod W], s < h'
+ *   Quadrant 2 [0;45]:   H2[s,x] = sum_y P [y, (x - D_h'(s,y)) mod W], s < h'
+ *   Quadrant 3 [45;90]:  H3[s,x] = sum_c Pt[c, (x - D_w'(s,c)) mod W], s < w'
+ *   Quadrant 4 [90;135]: H4[s,x] = sum_c Pt[c, (x + D_w'(s,c)) mod W], s < w'
+ *   (P = padded I, Pt = padded transpose of I.)
+ *   Full image (section 3.3): [flip(H1); H2[1:]; flip(H3)[1:]; H4[1:]], i.e.
+ *   2(w'+h')-3 rows of W columns.  Hough cell (x0, r) is at
+ *   hough[r * ld_hough + x0].
+ *
+ * Memory and streams.  Every image, Hough and workspace pointer is a DEVICE
+ * pointer owned by the caller; the library never frees or retains it.  Work
+ * is enqueued on `stream` (a hipStream_t; NULL = the default stream) and the
+ * call returns without synchronising.  No entry point allocates device memory
+ * except fht_batch_plan_create.  Scratch space comes from the caller's
+ * workspace, sized by the matching *_workspace_size query.
+ *
+ * Errors.  Every entry point validates its arguments before any HIP call.  On
+ * a negative status nothing has been enqueued and nothing written.  A launch
+ * failure returns FHT_ERR_HIP.  fht_last_error() returns a per-thread message
+ * for the last failure.
+ *
+ * Element types.  Allowed (input, accumulator) pairs: (FHT_U8, FHT_I32),
+ * (FHT_I32, FHT_I32), (FHT_F32, FHT_F32).  Integer results are exact while
+ * every partial sum fits in int32 (uint8 input: always, since 255 * 65536 <
+ * 2^31).  Float results use only binary32 additions in the stage order of the
+ * recurrence, so they are reproducible bit for bit.
+ */
+#ifndef FHT_H
+#define FHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fht_status {
+    FHT_OK = 0,
+    FHT_ERR_INVALID = -1,     /* bad pointer, size, leading dimension or flag */
+    FHT_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
+    FHT_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required */
+    FHT_ERR_HIP = -4,         /* a HIP runtime call or launch failed */
+    FHT_ERR_TIMEOUT = -5      /* a dependency wait in the batch kernel expired */
+};
+
+enum fht_dtype { FHT_U8 = 0, FHT_I32 = 1, FHT_F32 = 2 };
+
+/* Quadrant selection.  FHT_FULL (all four bits) produces the merged full image
+ * of section 3.3; any other non-empty subset produces the selected quadrants
+ * unmerged and unflipped, stacked in increasing quadrant order. */
+enum { FHT_Q1 = 1, FHT_Q2 = 2, FHT_Q3 = 4, FHT_Q4 = 8, FHT_FULL = 15 };
+
+/* fht_forward / fht_adjoint flags. */
+enum { FHT_FLAG_SHIFTED = 1 }; /* output (forward) or input (adjoint) is fhtshift-ed */
+
+/* Largest supported side (pow2-padded): 65536. */
+#define FHT_MAX_SIDE 65536
+
+int fht_version(void);
+const char* fht_status_string(int status);
+const char* fht_last_error(void);
+
+/*
+ * Shape of the Hough image for an h x w image and a quadrant selection
+ * (section 3.1 sizes; section 3.3 full size 2(w+h)-3).  Host-only, pure.
+ * FULL -> (2(w'+h')-3, W); Q1 or Q2 alone -> (h', W); Q3 or Q4 -> (w', W);
+ * other subsets -> the sum of the selected rows, W columns.
+ * Returns FHT_ERR_INVALID for w < 1, h < 1, an empty/unknown selection, null
+ * outputs or sides above FHT_MAX_SIDE.
+ */
+int fht_hough_shape(int w, int h, unsigned quads, int64_t* rows, int64_t* cols);
+
+/*
+ * Shape of the angle-range transform (section 4): (S+1, W).
+ * Requires 0 <= S <= n-1 and |S1| <= n-1, n = h' (w' when transposed).
+ */
+int fht_range_shape(int w, int h, int S1, int S, int transposed, int64_t* rows, int64_t* cols);
+
+/* Workspace bytes needed by fht_forward / fht_adjoint / fht_range. */
+int fht_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, size_t* bytes);
+int fht_range_workspace_size(int w, int h, int S1, int S, int transposed, int in_t, int acc_t,
+                             size_t* bytes);
+int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* bytes);
+
+/*
+ * Forward FHT (sections 3.1 and 3.3; fhtshift of section 5 with
+ * FHT_FLAG_SHIFTED).
+ *   img       device, h x w elements of in_t, row pitch ld_img >= w (elements)
+ *   hough     device, rows x cols of acc_t from fht_hough_shape, row pitch
+ *             ld_hough >= cols; every cell is written
+ *   workspace device, >= fht_workspace_size bytes, 256-byte aligned; its
+ *             contents on entry are ignored and on exit undefined
+ *   stream    hipStream_t or NULL
+ * img and hough must not overlap.
+ */
+int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t,
+                int64_t ld_hough, unsigned quads, unsigned flags, void* workspace,
+                size_t ws_bytes, void* stream);
+
+/*
+ * Angle-range transform (section 4).  Shifts s = 0..S of quadrant 1 (quadrant
+ * 4 of the transposed image when transposed != 0) computed on the image whose
+ * row y is read cyclically pre-shifted right by
+ *   sigma(y) = floor((2*y*S1 + (n-1)) / (2*(n-1)))   (n = h' or w'),
+ * inside the first stage, without a sheared copy.  Row s then holds the sums
+ * along patterns of slope (s - S1)/(n-1) columns per row; stages compute only
+ * the shifts that some output row s <= S depends on.
+ *   hough  device, (S+1) x W of acc_t, pitch ld_hough >= W.
+ * Requirements as for fht_range_shape.
+ */
+int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, int S,
+              int transposed, void* hough, int acc_t, int64_t ld_hough, void* workspace,
+              size_t ws_bytes, void* stream);
+
+/*
+ * fhtshift of a full Hough image (section 5), or its inverse.  Row r of local
+ * shift s in quadrant q is rolled right cyclically by
+ *   q1: floor((h'+s)/2)  q2: floor((h'-s)/2)  q3: floor((w'-s)/2)  q4: floor((w'+s)/2)
+ * (left by the same amounts when inverse != 0), which centres each row's
+ * meaningful run of w'+s (vertical) or h'+s (horizontal) cells.
+ *   in, out  device, (2(w'+h')-3) x W of t (FHT_I32 or FHT_F32), pitches
+ *            ld_in, ld_out >= W.  out == in (same pitch) rolls in place and
+ *            needs W * 4 <= 163840; other overlaps are invalid.
+ */
+int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, int w, int h,
+              int inverse, void* stream);
+
+/*
+ * Adjoint (transpose) of fht_forward: grad_img = F^T grad_hough, i.e. every
+ * Hough cell's value is added back onto the pixels of its pattern (dyadic
+ * back-projection), cropped to the h x w image; with FHT_FULL the dropped
+ * duplicate junction rows contribute nothing.  Used as the backward of the
+ * forward transform.
+ *   grad_hough device, shape of fht_hough_shape(w, h, quads) of t, pitch
+ *              ld_hough; fhtshift-ed when flags has FHT_FLAG_SHIFTED
+ *   grad_img   device, h x w of t, pitch ld_img >= w; fully overwritten
+ *   t          FHT_I32 or FHT_F32 (the accumulator type of the forward)
+ */
+int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img, int64_t ld_img,
+                int w, int h, unsigned quads, unsigned flags, void* workspace, size_t ws_bytes,
+                void* stream);
+
+/*
+ * Batched forward over many images of different sizes, executed by one
+ * persistent kernel launch (ordered work queue with per-pass dependency
+ * counters) that fht_batch_forward enqueues on the stream; the launch can be
+ * captured in a hipGraph once the plan exists.  Each image is transformed as
+ * by fht_forward(quads, flags = 0) into its own slice of one packed output
+ * buffer.
+ *
+ * fht_batch_plan_create: ws[i], hs[i] are the n image sizes (host arrays).
+ *   Allocates the plan's device tables (the only allocating entry point).
+ *   *ws_bytes receives the workspace size, *out_elems the total number of
+ *   output elements; out_offsets (host, n entries, may be NULL) receives each
+ *   image's element offset in the packed output (each image's Hough image is
+ *   stored densely, ld_hough = W_i).
+ * fht_batch_forward: imgs is a DEVICE array of n device pointers (image i
+ *   dense, ld = w_i); hough is the packed output.
+ */
+typedef struct fht_batch_plan fht_batch_plan;
+int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned quads, int in_t,
+                          int acc_t, fht_batch_plan** plan, size_t* ws_bytes, int64_t* out_elems,
+                          int64_t* out_offsets);
+int fht_batch_forward(const fht_batch_plan* plan, const void* const* imgs, void* hough,
+                      void* workspace, size_t ws_bytes, void* stream);
+int fht_batch_plan_destroy(fht_batch_plan* plan);
+
+/* Stage-fusion split chosen for a side (number of passes and stages per pass),
+ * for inspection and tests.  passes[] receives up to 4 entries. */
+int fht_pass_split(int side, int* npass, int* passes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHT_H */

@@ -1,0 +1,541 @@
+// C ABI of libfht.so (declared in include/fht.h): argument validation, pass
+// planning, workspace layout and launch orchestration.  All arithmetic runs in
+// the kernels of fht_kernels.hip and fht_batch.hip.
+
+#include "fht.h"
+#include "fht_internal.h"
+#include "fht_plan.h"
+
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace fht {
+
+static thread_local char g_last_error[512] = "";
+
+int fail(int status, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(FHT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t pow2_ceil(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int ilog2(int64_t p)
+{
+    int k = 0;
+    while ((int64_t(1) << k) < p) ++k;
+    return k;
+}
+
+void pass_split(int k, int* npass, int* G)
+{
+    if (k <= 2) {
+        *npass = 1;
+        G[0] = k;
+        return;
+    }
+    const int np = (k + kMaxG - 1) / kMaxG;
+    const int base = k / np, rem = k % np;
+    for (int i = 0; i < np; ++i) G[i] = base + (i < rem ? 1 : 0);
+    *npass = np;
+}
+
+// Geometry of quadrant q (1..4) of an h x w image; S1 != 0 adds the range shear.
+QuadGeom quad_geom(int w, int h, int q, int S1)
+{
+    QuadGeom g{};
+    const int hp = (int)pow2_ceil(h), wp = (int)pow2_ceil(w);
+    g.q = q;
+    g.transposed = q >= 3;
+    g.n = g.transposed ? wp : hp;
+    g.other = g.transposed ? hp : wp;
+    g.W = hp + wp;
+    g.k = ilog2(g.n);
+    g.dir = (q == 1 || q == 4) ? 1 : -1;
+    pass_split(g.k, &g.npass, g.G);
+    int j = 0;
+    for (int p = 0; p < g.npass; ++p) {
+        j += g.G[p];
+        g.j_end[p] = j;
+        // nonzero logical columns after j stages: the image's columns moved by
+        // the shear (rows roll right by 0..S1) widened by 2^j - 1 on the side the
+        // patterns lean to
+        const int64_t spread = (int64_t(1) << j) - 1;
+        int64_t lo = (S1 < 0 ? S1 : 0) - (g.dir > 0 ? spread : 0);
+        int64_t hi = (S1 > 0 ? S1 : 0) + g.other + (g.dir < 0 ? spread : 0);
+        int64_t bw = hi - lo;
+        if (bw > g.W) bw = g.W;
+        g.band_off[p] = (int)(-lo);
+        g.band_w[p] = (int)bw;
+        g.band_ld[p] = (bw + 63) / 64 * 64;
+    }
+    return g;
+}
+
+size_t quad_band_bytes(const QuadGeom& g, int p, int elem)
+{
+    return ((size_t)g.n * (size_t)g.band_ld[p] * (size_t)elem + 255) / 256 * 256;
+}
+
+// Lays out the intermediate bands of the selected quadrants; returns total bytes.
+size_t layout_bands(QuadGeom* gs, int nq, int elem)
+{
+    size_t off = 0;
+    for (int i = 0; i < nq; ++i)
+        for (int p = 0; p + 1 < gs[i].npass; ++p) {
+            gs[i].band_byte_off[p] = off;
+            off += quad_band_bytes(gs[i], p, elem);
+        }
+    return off;
+}
+
+static bool dtype_pair_ok(int in_t, int acc_t)
+{
+    return (in_t == FHT_U8 && acc_t == FHT_I32) || (in_t == FHT_I32 && acc_t == FHT_I32) ||
+           (in_t == FHT_F32 && acc_t == FHT_F32);
+}
+
+static int elem_size(int t) { return t == FHT_U8 ? 1 : 4; }
+
+int check_sides(int w, int h)
+{
+    if (w < 1 || h < 1) return fail(FHT_ERR_INVALID, "image sides must be >= 1 (got w=%d h=%d)", w, h);
+    if (pow2_ceil(w) > FHT_MAX_SIDE || pow2_ceil(h) > FHT_MAX_SIDE)
+        return fail(FHT_ERR_INVALID, "padded side exceeds %d", FHT_MAX_SIDE);
+    return FHT_OK;
+}
+
+int selected_quads(unsigned quads, int* qs)
+{
+    int nq = 0;
+    for (int q = 1; q <= 4; ++q)
+        if (quads & (1u << (q - 1))) qs[nq++] = q;
+    return nq;
+}
+
+// Hough row placement of quadrant q's shift s.
+void placement(int w, int h, unsigned quads, int q, int* base, int* sign, int* skip, int* roll_a,
+               int* roll_b)
+{
+    const int hp = (int)pow2_ceil(h), wp = (int)pow2_ceil(w);
+    *roll_a = (q <= 2) ? hp : wp;
+    *roll_b = (q == 1 || q == 4) ? 1 : -1;
+    if (quads == FHT_FULL) {
+        // section 3.3: flip(H1); H2[1:]; flip(H3)[1:]; H4[1:]
+        switch (q) {
+        case 1: *base = hp - 1; *sign = -1; *skip = -1; break;
+        case 2: *base = hp - 1; *sign = 1; *skip = 0; break;
+        case 3: *base = 2 * hp + wp - 3; *sign = -1; *skip = wp - 1; break;
+        default: *base = 2 * hp + wp - 3; *sign = 1; *skip = 0; break;
+        }
+        return;
+    }
+    int off = 0;
+    for (int p = 1; p < q; ++p)
+        if (quads & (1u << (p - 1))) off += (p <= 2) ? hp : wp;
+    *base = off;
+    *sign = 1;
+    *skip = -1;
+}
+
+}  // namespace fht
+
+using namespace fht;
+
+extern "C" {
+
+int fht_version(void) { return 10000; }
+
+const char* fht_status_string(int status)
+{
+    switch (status) {
+    case FHT_OK: return "ok";
+    case FHT_ERR_INVALID: return "invalid argument";
+    case FHT_ERR_UNSUPPORTED: return "unsupported request";
+    case FHT_ERR_WORKSPACE: return "workspace missing or too small";
+    case FHT_ERR_HIP: return "HIP runtime error";
+    case FHT_ERR_TIMEOUT: return "dependency wait timed out";
+    default: return "unknown status";
+    }
+}
+
+const char* fht_last_error(void) { return g_last_error; }
+
+int fht_pass_split(int side, int* npass, int* passes)
+{
+    if (!npass || !passes) return fail(FHT_ERR_INVALID, "null output");
+    if (side < 1 || pow2_ceil(side) > FHT_MAX_SIDE) return fail(FHT_ERR_INVALID, "bad side %d", side);
+    int G[4];
+    pass_split(ilog2(pow2_ceil(side)), npass, G);
+    for (int i = 0; i < *npass; ++i) passes[i] = G[i];
+    return FHT_OK;
+}
+
+int fht_hough_shape(int w, int h, unsigned quads, int64_t* rows, int64_t* cols)
+{
+    if (!rows || !cols) return fail(FHT_ERR_INVALID, "null shape output");
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    if (quads == 0 || (quads & ~15u)) return fail(FHT_ERR_INVALID, "bad quadrant selection 0x%x", quads);
+    const int64_t hp = pow2_ceil(h), wp = pow2_ceil(w);
+    *cols = hp + wp;
+    if (quads == FHT_FULL) {
+        *rows = 2 * (hp + wp) - 3;
+    } else {
+        int64_t r = 0;
+        for (int q = 1; q <= 4; ++q)
+            if (quads & (1u << (q - 1))) r += (q <= 2) ? hp : wp;
+        *rows = r;
+    }
+    return FHT_OK;
+}
+
+int fht_range_shape(int w, int h, int S1, int S, int transposed, int64_t* rows, int64_t* cols)
+{
+    if (!rows || !cols) return fail(FHT_ERR_INVALID, "null shape output");
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    const int64_t hp = pow2_ceil(h), wp = pow2_ceil(w);
+    const int64_t n = transposed ? wp : hp;
+    if (S < 0 || S > n - 1) return fail(FHT_ERR_INVALID, "S=%d outside [0, %lld]", S, (long long)(n - 1));
+    if (S1 > n - 1 || S1 < -(n - 1)) return fail(FHT_ERR_INVALID, "|S1|=%d exceeds %lld", S1, (long long)(n - 1));
+    *rows = (int64_t)S + 1;
+    *cols = hp + wp;
+    return FHT_OK;
+}
+
+int fht_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, size_t* bytes)
+{
+    if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
+    int64_t r, c;
+    int rc = fht_hough_shape(w, h, quads, &r, &c);
+    if (rc) return rc;
+    if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    *bytes = layout_bands(gs, nq, elem_size(acc_t));
+    return FHT_OK;
+}
+
+int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* bytes)
+{
+    if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "adjoint type must be I32 or F32");
+    return fht_workspace_size(w, h, quads, t, t, bytes);
+}
+
+int fht_range_workspace_size(int w, int h, int S1, int S, int transposed, int in_t, int acc_t, size_t* bytes)
+{
+    if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
+    int64_t r, c;
+    int rc = fht_range_shape(w, h, S1, S, transposed, &r, &c);
+    if (rc) return rc;
+    if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    QuadGeom g = quad_geom(w, h, transposed ? 4 : 1, S1);
+    *bytes = layout_bands(&g, 1, elem_size(acc_t));
+    return FHT_OK;
+}
+
+}  // extern "C"
+
+namespace fht {
+
+// Fills the descriptor of forward pass p of quadrant geometry g.
+PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int in_src_kind, int w, int h,
+                        int64_t ld_img, void* hough, int64_t ld_hough, unsigned char* ws, int S1,
+                        int row_limit_final, int base, int sign, int skip, int shifted, int roll_a,
+                        int roll_b)
+{
+    PassDesc d{};
+    const int G = g.G[p];
+    const int VW = kWinCols - (1 << G);
+    d.n = g.n;
+    d.W = g.W;
+    d.j0 = p == 0 ? 0 : g.j_end[p - 1];
+    d.dir = g.dir;
+    d.img_w = w;
+    d.img_h = h;
+    d.n_row_tiles = (g.n + kTileRows - 1) / kTileRows;
+    if (p == 0) {
+        d.src = img;
+        d.src_ld = ld_img;
+        d.src_kind = in_src_kind;
+        d.S1 = S1;
+    } else {
+        d.src = ws + g.band_byte_off[p - 1];
+        d.src_ld = g.band_ld[p - 1];
+        d.src_kind = SRC_BAND;
+        d.src_off = g.band_off[p - 1];
+        d.src_bw = g.band_w[p - 1];
+    }
+    const bool last = p == g.npass - 1;
+    if (last) {
+        d.dst = hough;
+        d.dst_ld = ld_hough;
+        d.dst_kind = DST_HOUGH;
+        d.x_start = 0;
+        d.n_windows = (g.W + VW - 1) / VW;
+        d.row_limit = row_limit_final;
+        d.row_base = base;
+        d.row_sign = sign;
+        d.skip_row = skip;
+        d.shifted = shifted;
+        d.roll_a = roll_a;
+        d.roll_b = roll_b;
+    } else {
+        d.dst = ws + g.band_byte_off[p];
+        d.dst_ld = g.band_ld[p];
+        d.dst_kind = DST_BAND;
+        d.dst_off = g.band_off[p];
+        d.dst_bw = g.band_w[p];
+        d.x_start = -g.band_off[p];
+        d.n_windows = (g.band_w[p] + VW - 1) / VW;
+        d.row_limit = row_limit_final == INT_MAX ? INT_MAX : (row_limit_final >> (g.k - g.j_end[p]));
+        d.skip_row = -1;
+    }
+    return d;
+}
+
+// Runs the forward passes of the quadrant geometries gs[0..nq) (all already
+// described by descs[i][p]); one launch per (pass index, fusion depth).
+int run_forward_passes(const QuadGeom* gs, PassDesc (*descs)[4], int nq, int in_t, int acc_t,
+                       hipStream_t stream)
+{
+    int maxp = 0;
+    for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
+    for (int p = 0; p < maxp; ++p) {
+        for (int G = 0; G <= kMaxG; ++G) {
+            PassLaunch L{};
+            for (int i = 0; i < nq; ++i)
+                if (p < gs[i].npass && gs[i].G[p] == G) L.d[L.nd++] = descs[i][p];
+            if (L.nd == 0) continue;
+            const int ti = p == 0 ? in_t : acc_t;
+            hipError_t e = G <= 2 ? launch_direct(L, G, ti, acc_t, stream) : launch_pass(L, G, ti, acc_t, stream);
+            if (e != hipSuccess) return hip_fail(e, "forward pass launch");
+        }
+    }
+    return FHT_OK;
+}
+
+}  // namespace fht
+
+extern "C" {
+
+int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t,
+                int64_t ld_hough, unsigned quads, unsigned flags, void* workspace, size_t ws_bytes,
+                void* stream)
+{
+    int64_t rows, cols;
+    int rc = fht_hough_shape(w, h, quads, &rows, &cols);
+    if (rc) return rc;
+    if (!img || !hough) return fail(FHT_ERR_INVALID, "null image or Hough pointer");
+    if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
+    if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
+    if (flags & ~(unsigned)FHT_FLAG_SHIFTED) return fail(FHT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if ((flags & FHT_FLAG_SHIFTED) && quads != FHT_FULL)
+        return fail(FHT_ERR_INVALID, "fhtshift applies to the full Hough image only");
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    const size_t need = layout_bands(gs, nq, elem_size(acc_t));
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if (workspace && ((uintptr_t)workspace & 255))
+        return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    PassDesc descs[4][4];
+    for (int i = 0; i < nq; ++i) {
+        int base, sign, skip, ra, rb;
+        placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
+        for (int p = 0; p < gs[i].npass; ++p)
+            descs[i][p] = make_pass_desc(gs[i], p, img, gs[i].transposed ? SRC_IMAGE_T : SRC_IMAGE, w, h,
+                                         ld_img, hough, ld_hough, (unsigned char*)workspace, 0, INT_MAX,
+                                         base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb);
+    }
+    return run_forward_passes(gs, descs, nq, in_t, acc_t, (hipStream_t)stream);
+}
+
+int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, int S, int transposed,
+              void* hough, int acc_t, int64_t ld_hough, void* workspace, size_t ws_bytes, void* stream)
+{
+    int64_t rows, cols;
+    int rc = fht_range_shape(w, h, S1, S, transposed, &rows, &cols);
+    if (rc) return rc;
+    if (!img || !hough) return fail(FHT_ERR_INVALID, "null image or Hough pointer");
+    if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
+    if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
+    QuadGeom g = quad_geom(w, h, transposed ? 4 : 1, S1);
+    const size_t need = layout_bands(&g, 1, elem_size(acc_t));
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if (workspace && ((uintptr_t)workspace & 255))
+        return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    PassDesc descs[1][4];
+    for (int p = 0; p < g.npass; ++p)
+        descs[0][p] = make_pass_desc(g, p, img, transposed ? SRC_IMAGE_T : SRC_IMAGE, w, h, ld_img, hough,
+                                     ld_hough, (unsigned char*)workspace, S1, S, 0, 1, -1, 0, 0, 0);
+    return run_forward_passes(&g, descs, 1, in_t, acc_t, (hipStream_t)stream);
+}
+
+int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, int w, int h, int inverse,
+              void* stream)
+{
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    if (!in || !out) return fail(FHT_ERR_INVALID, "null pointer");
+    if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "fht_shift type must be I32 or F32");
+    const int64_t hp = pow2_ceil(h), wp = pow2_ceil(w), W = hp + wp, rows = 2 * (hp + wp) - 3;
+    if (ld_in < W || ld_out < W) return fail(FHT_ERR_INVALID, "pitch smaller than W=%lld", (long long)W);
+    const char* a0 = (const char*)in;
+    const char* a1 = a0 + (size_t)((rows - 1) * ld_in + W) * 4;
+    const char* b0 = (const char*)out;
+    const char* b1 = b0 + (size_t)((rows - 1) * ld_out + W) * 4;
+    const bool same = (in == out) && ld_in == ld_out;
+    if (!same && a0 < b1 && b0 < a1) return fail(FHT_ERR_INVALID, "in and out overlap without being identical");
+    if (same && W * 4 > 163840) return fail(FHT_ERR_UNSUPPORTED, "in-place fhtshift needs W*4 <= 163840");
+    hipError_t e = launch_shift(in, ld_in, out, ld_out, 4, (int)hp, (int)wp, inverse ? 1 : 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fht_shift launch");
+    return FHT_OK;
+}
+
+}  // extern "C"
+
+namespace fht {
+
+AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_grad, void* gimg, int64_t ld_img,
+                      int w, int h, unsigned char* ws, int base, int sign, int skip, int shifted, int roll_a,
+                      int roll_b, int accumulate)
+{
+    AdjDesc d{};
+    const int G = g.G[p];
+    const int VW = kWinCols - (1 << G);
+    d.n = g.n;
+    d.W = g.W;
+    d.j0 = p == 0 ? 0 : g.j_end[p - 1];
+    d.dir = g.dir;
+    d.img_w = w;
+    d.img_h = h;
+    d.n_row_tiles = (g.n + kTileRows - 1) / kTileRows;
+    if (p == g.npass - 1) {
+        d.src = grad;
+        d.src_ld = ld_grad;
+        d.src_kind = 0;
+        d.row_base = base;
+        d.row_sign = sign;
+        d.skip_row = skip;
+        d.shifted = shifted;
+        d.roll_a = roll_a;
+        d.roll_b = roll_b;
+    } else {
+        d.src = ws + g.band_byte_off[p];
+        d.src_ld = g.band_ld[p];
+        d.src_kind = 1;
+        d.src_off = g.band_off[p];
+        d.src_bw = g.band_w[p];
+        d.skip_row = -1;
+    }
+    if (p == 0) {
+        d.dst = gimg;
+        d.dst_ld = ld_img;
+        d.dst_kind = g.transposed ? 2 : 1;
+        d.accumulate = accumulate;
+        const int cols = g.transposed ? h : w;
+        d.x_start = 0;
+        d.n_windows = (cols + VW - 1) / VW;
+    } else {
+        d.dst = ws + g.band_byte_off[p - 1];
+        d.dst_ld = g.band_ld[p - 1];
+        d.dst_kind = 0;
+        d.dst_off = g.band_off[p - 1];
+        d.dst_bw = g.band_w[p - 1];
+        d.x_start = 0;
+        d.n_windows = (g.W + VW - 1) / VW;
+    }
+    return d;
+}
+
+}  // namespace fht
+
+extern "C" {
+
+int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img, int64_t ld_img, int w, int h,
+                unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream)
+{
+    int64_t rows, cols;
+    int rc = fht_hough_shape(w, h, quads, &rows, &cols);
+    if (rc) return rc;
+    if (!grad_hough || !grad_img) return fail(FHT_ERR_INVALID, "null gradient pointer");
+    if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "adjoint type must be I32 or F32");
+    if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
+    if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
+    if (flags & ~(unsigned)FHT_FLAG_SHIFTED) return fail(FHT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if ((flags & FHT_FLAG_SHIFTED) && quads != FHT_FULL)
+        return fail(FHT_ERR_INVALID, "fhtshift applies to the full Hough image only");
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    const size_t need = layout_bands(gs, nq, 4);
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if (workspace && ((uintptr_t)workspace & 255))
+        return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    AdjDesc descs[4][4];
+    for (int i = 0; i < nq; ++i) {
+        int base, sign, skip, ra, rb;
+        placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
+        for (int p = 0; p < gs[i].npass; ++p)
+            descs[i][p] = make_adj_desc(gs[i], p, grad_hough, ld_hough, grad_img, ld_img, w, h,
+                                        (unsigned char*)workspace, base, sign, skip,
+                                        (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, i > 0 ? 1 : 0);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int maxp = 0;
+    for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
+    // adjoint passes in reverse order; the passes writing the image go one
+    // quadrant at a time, in quadrant order, so the sum is formed as
+    // ((q1 + q2) + q3) + q4
+    for (int p = maxp - 1; p >= 0; --p) {
+        if (p > 0) {
+            for (int G = 3; G <= kMaxG; ++G) {
+                AdjLaunch L{};
+                for (int i = 0; i < nq; ++i)
+                    if (p < gs[i].npass && gs[i].G[p] == G) L.d[L.nd++] = descs[i][p];
+                if (L.nd == 0) continue;
+                hipError_t e = launch_adjoint_pass(L, G, t, s);
+                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+            }
+        } else {
+            for (int i = 0; i < nq; ++i) {
+                AdjLaunch L{};
+                L.d[0] = descs[i][0];
+                L.nd = 1;
+                const int G = gs[i].G[0];
+                hipError_t e = G <= 2 ? launch_adjoint_direct(L, G, t, s) : launch_adjoint_pass(L, G, t, s);
+                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+            }
+        }
+    }
+    return FHT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Type dispatch of the pass launchers, plus the fhtshift and fill kernels'
+// launchers.
+#include "fht_launch.h"
+
+namespace fht {
+
+__global__ void fht_zero_kernel(uint32_t* p, int64_t rows, int64_t cols_words, int64_t ld_words)
+{
+    const int64_t total = rows * cols_words;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / cols_words, c = i - r * cols_words;
+        p[r * ld_words + c] = 0u;
+    }
+}
+
+// dtype codes: 0 = u8, 1 = i32, 2 = f32
+hipError_t launch_pass(const PassLaunch& L, int G, int in_t, int acc_t, hipStream_t s)
+{
+    if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, G, s);
+    if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, G, s);
+    if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, G, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s)
+{
+    if (in_t == 0 && acc_t == 1) return launch_direct_u8(L, k, s);
+    if (in_t == 1 && acc_t == 1) return launch_direct_i32(L, k, s);
+    if (in_t == 2 && acc_t == 2) return launch_direct_f32(L, k, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_pass(const AdjLaunch& L, int G, int t, hipStream_t s)
+{
+    if (t == 1) return launch_adj_pass_i32(L, G, s);
+    if (t == 2) return launch_adj_pass_f32(L, G, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s)
+{
+    if (t == 1) return launch_adj_direct_i32(L, k, s);
+    if (t == 2) return launch_adj_direct_f32(L, k, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s)
+{
+    if (elem_bytes != 4) return hipErrorInvalidValue;
+    const int64_t total = rows * cols;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fht_zero_kernel, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, rows, cols, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,
+                        int hp, int wp, int inverse, hipStream_t s)
+{
+    if (elem_bytes != 4) return hipErrorInvalidValue;
+    const int W = hp + wp;
+    const int rows = 2 * (hp + wp) - 3;
+    if (in == out && ld_in == ld_out) {
+        const size_t lds_bytes = (size_t)W * 4;
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void*)fht_shift_inplace_kernel<uint32_t>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(fht_shift_inplace_kernel<uint32_t>, dim3(rows), dim3(1024), lds_bytes, s,
+                           (uint32_t*)out, ld_out, hp, wp, inverse);
+    } else {
+        hipLaunchKernelGGL(fht_shift_kernel<uint32_t>, dim3((W + 255) / 256, rows), dim3(256), 0, s,
+                           (const uint32_t*)in, ld_in, (uint32_t*)out, ld_out, hp, wp, inverse);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fht

@@ -1,0 +1,354 @@
+"""Python binding of libfht.so (ctypes).  Argument marshalling only.
+
+Every transform runs in the library's HIP kernels; torch supplies device
+memory (tensors) and the current HIP stream.  If the library is missing the
+calls raise instead of falling back to anything else.
+
+Names follow the C ABI in include/fht.h:
+  forward(img, quads='full', shifted=False)   sections 3.1, 3.3 (and 5)
+  range_transform(img, S1, S, transposed)     section 4
+  shift(hough, w, h, inverse)                 section 5 (fhtshift)
+  adjoint(grad, w, h, quads, shifted)         transpose of forward
+  FHTFunction                                 autograd wrapper
+  BatchPlan                                   batched forward (one persistent launch)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfht.so")
+
+FHT_OK, FHT_ERR_INVALID, FHT_ERR_UNSUPPORTED, FHT_ERR_WORKSPACE, FHT_ERR_HIP, FHT_ERR_TIMEOUT = 0, -1, -2, -3, -4, -5
+FHT_U8, FHT_I32, FHT_F32 = 0, 1, 2
+FHT_Q1, FHT_Q2, FHT_Q3, FHT_Q4, FHT_FULL = 1, 2, 4, 8, 15
+FHT_FLAG_SHIFTED = 1
+
+_lock = threading.Lock()
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_U = ctypes.c_uint
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PSZ = ctypes.POINTER(ctypes.c_size_t)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+
+# symbol -> (restype, argtypes); the full ABI of include/fht.h
+SIGNATURES = {
+    "fht_version": (_I, []),
+    "fht_status_string": (ctypes.c_char_p, [_I]),
+    "fht_last_error": (ctypes.c_char_p, []),
+    "fht_hough_shape": (_I, [_I, _I, _U, _PI64, _PI64]),
+    "fht_range_shape": (_I, [_I, _I, _I, _I, _I, _PI64, _PI64]),
+    "fht_workspace_size": (_I, [_I, _I, _U, _I, _I, _PSZ]),
+    "fht_range_workspace_size": (_I, [_I, _I, _I, _I, _I, _I, _I, _PSZ]),
+    "fht_adjoint_workspace_size": (_I, [_I, _I, _U, _I, _PSZ]),
+    "fht_forward": (_I, [_P, _I, _I, _I, _I64, _P, _I, _I64, _U, _U, _P, _SZ, _P]),
+    "fht_range": (_I, [_P, _I, _I, _I, _I64, _I, _I, _I, _P, _I, _I64, _P, _SZ, _P]),
+    "fht_shift": (_I, [_P, _I64, _P, _I64, _I, _I, _I, _I, _P]),
+    "fht_adjoint": (_I, [_P, _I, _I64, _P, _I64, _I, _I, _U, _U, _P, _SZ, _P]),
+    "fht_batch_plan_create": (_I, [_PI32, _PI32, _I, _U, _I, _I, ctypes.POINTER(_P), _PSZ, _PI64, _PI64]),
+    "fht_batch_forward": (_I, [_P, _P, _P, _P, _SZ, _P]),
+    "fht_batch_plan_destroy": (_I, [_P]),
+    "fht_pass_split": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+}
+
+
+class FHTError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libfht.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise FHTError("libfht.so is not built (run __graft_entry__.build() or "
+                               "python paper_1811_06378_amd/build.py); there is no fallback path")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc == FHT_OK:
+        return
+    L = lib()
+    msg = "%s: %s (%s)" % (what, L.fht_status_string(rc).decode(), L.fht_last_error().decode())
+    if rc in (FHT_ERR_INVALID, FHT_ERR_UNSUPPORTED, FHT_ERR_WORKSPACE):
+        raise ValueError(msg)
+    raise FHTError(msg)
+
+
+_QUADS = {"full": FHT_FULL, "q1": FHT_Q1, "q2": FHT_Q2, "q3": FHT_Q3, "q4": FHT_Q4}
+
+
+def _quads(q) -> int:
+    if isinstance(q, int):
+        return q
+    if isinstance(q, str):
+        return _QUADS[q]
+    m = 0
+    for x in q:
+        m |= 1 << (int(x) - 1)
+    return m
+
+
+def _dtypes(t: torch.dtype):
+    if t == torch.uint8:
+        return FHT_U8, FHT_I32, torch.int32
+    if t == torch.int32:
+        return FHT_I32, FHT_I32, torch.int32
+    if t == torch.float32:
+        return FHT_F32, FHT_F32, torch.float32
+    raise ValueError("unsupported image dtype %s (uint8, int32 or float32)" % t)
+
+
+def _acc_code(t: torch.dtype) -> int:
+    if t == torch.int32:
+        return FHT_I32
+    if t == torch.float32:
+        return FHT_F32
+    raise ValueError("Hough dtype must be int32 or float32")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_2d(x: torch.Tensor, name: str):
+    if not x.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("%s must be 2-D with unit column stride" % name)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # 256-byte aligned by the caching allocator
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def hough_shape(w: int, h: int, quads="full"):
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fht_hough_shape(w, h, _quads(quads), ctypes.byref(r), ctypes.byref(c)), "fht_hough_shape")
+    return r.value, c.value
+
+
+def range_shape(w: int, h: int, S1: int, S: int, transposed: bool = False):
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fht_range_shape(w, h, S1, S, int(transposed), ctypes.byref(r), ctypes.byref(c)),
+           "fht_range_shape")
+    return r.value, c.value
+
+
+def pass_split(side: int):
+    n = ctypes.c_int()
+    arr = (ctypes.c_int * 4)()
+    _check(lib().fht_pass_split(side, ctypes.byref(n), arr), "fht_pass_split")
+    return [arr[i] for i in range(n.value)]
+
+
+def workspace_size(w: int, h: int, quads="full", in_dtype=torch.float32) -> int:
+    it, at, _ = _dtypes(in_dtype)
+    b = ctypes.c_size_t()
+    _check(lib().fht_workspace_size(w, h, _quads(quads), it, at, ctypes.byref(b)), "fht_workspace_size")
+    return b.value
+
+
+def forward(img: torch.Tensor, quads="full", shifted: bool = False, out: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Hough image of a 2-D device image (uint8 -> int32, int32, float32)."""
+    _check_2d(img, "img")
+    h, w = img.shape
+    it, at, odt = _dtypes(img.dtype)
+    q = _quads(quads)
+    rows, cols = hough_shape(w, h, q)
+    if out is None:
+        out = torch.empty((rows, cols), dtype=odt, device=img.device)
+    _check_2d(out, "out")
+    if out.shape[0] != rows or out.shape[1] != cols or out.dtype != odt:
+        raise ValueError("out must be %dx%d %s" % (rows, cols, odt))
+    nb = workspace_size(w, h, q, img.dtype)
+    if workspace is None:
+        workspace = _workspace(nb, img.device)
+    rc = lib().fht_forward(img.data_ptr(), it, w, h, img.stride(0), out.data_ptr(), at, out.stride(0), q,
+                           FHT_FLAG_SHIFTED if shifted else 0, workspace.data_ptr(),
+                           workspace.numel() * workspace.element_size(), _stream())
+    _check(rc, "fht_forward")
+    return out
+
+
+def range_params(n: int, deg_lo: float, deg_hi: float):
+    """Integer range (S1, S) covering inclinations [deg_lo, deg_hi] (degrees
+    from the vertical, positive = leaning right as y grows) for n pattern rows:
+    shifts 0..S hold slopes (s - S1)/(n-1)."""
+    if n <= 1:
+        return 0, 0
+    lo = (n - 1) * math.tan(math.radians(deg_lo))
+    hi = (n - 1) * math.tan(math.radians(deg_hi))
+    S1 = -math.floor(lo)
+    S = math.ceil(hi) - math.floor(lo)
+    return int(S1), int(S)
+
+
+def range_transform(img: torch.Tensor, S1: int, S: int, transposed: bool = False,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """Angle-range transform (section 4): (S+1) x W."""
+    _check_2d(img, "img")
+    h, w = img.shape
+    it, at, odt = _dtypes(img.dtype)
+    rows, cols = range_shape(w, h, S1, S, transposed)
+    if out is None:
+        out = torch.empty((rows, cols), dtype=odt, device=img.device)
+    _check_2d(out, "out")
+    b = ctypes.c_size_t()
+    _check(lib().fht_range_workspace_size(w, h, S1, S, int(transposed), it, at, ctypes.byref(b)),
+           "fht_range_workspace_size")
+    ws = _workspace(b.value, img.device)
+    rc = lib().fht_range(img.data_ptr(), it, w, h, img.stride(0), S1, S, int(transposed), out.data_ptr(), at,
+                         out.stride(0), ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, "fht_range")
+    return out
+
+
+def range_degrees(img: torch.Tensor, deg_lo: float, deg_hi: float, transposed: bool = False):
+    h, w = img.shape
+    n = 1 << max(0, (int(w if transposed else h) - 1).bit_length())
+    S1, S = range_params(n, deg_lo, deg_hi)
+    return range_transform(img, S1, S, transposed), (S1, S)
+
+
+def shift(hough: torch.Tensor, w: int, h: int, inverse: bool = False, out: torch.Tensor | None = None):
+    """fhtshift (section 5) of a full Hough image; out=hough rolls in place."""
+    _check_2d(hough, "hough")
+    t = _acc_code(hough.dtype)
+    if out is None:
+        out = torch.empty_like(hough)
+    _check_2d(out, "out")
+    rc = lib().fht_shift(hough.data_ptr(), hough.stride(0), out.data_ptr(), out.stride(0), t, w, h,
+                         int(inverse), _stream())
+    _check(rc, "fht_shift")
+    return out
+
+
+def adjoint(grad: torch.Tensor, w: int, h: int, quads="full", shifted: bool = False,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    """Transpose of forward: Hough-shaped gradient -> h x w image gradient."""
+    _check_2d(grad, "grad")
+    t = _acc_code(grad.dtype)
+    q = _quads(quads)
+    if out is None:
+        out = torch.empty((h, w), dtype=grad.dtype, device=grad.device)
+    _check_2d(out, "out")
+    b = ctypes.c_size_t()
+    _check(lib().fht_adjoint_workspace_size(w, h, q, t, ctypes.byref(b)), "fht_adjoint_workspace_size")
+    ws = _workspace(b.value, grad.device)
+    rc = lib().fht_adjoint(grad.data_ptr(), t, grad.stride(0), out.data_ptr(), out.stride(0), w, h, q,
+                           FHT_FLAG_SHIFTED if shifted else 0, ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, "fht_adjoint")
+    return out
+
+
+class FHTFunction(torch.autograd.Function):
+    """Differentiable full (or partial) Hough transform of float32 images.
+
+    forward: H = F(img) by the library's forward kernels; backward: the
+    gradient w.r.t. img is F^T(dL/dH) by the library's adjoint kernels.
+    Accepts (h, w) or (batch, h, w).
+    """
+
+    @staticmethod
+    def forward(ctx, img, quads="full", shifted=False):
+        if img.dtype != torch.float32:
+            raise ValueError("FHTFunction works on float32 images")
+        ctx.quads, ctx.shifted = quads, shifted
+        ctx.hw = tuple(img.shape[-2:])
+        x = img.contiguous()
+        if x.dim() == 2:
+            return forward(x, quads, shifted)
+        outs = [forward(x[i], quads, shifted) for i in range(x.shape[0])]
+        return torch.stack(outs)
+
+    @staticmethod
+    def backward(ctx, g):
+        h, w = ctx.hw
+        g = g.contiguous()
+        if g.dim() == 2:
+            return adjoint(g, w, h, ctx.quads, ctx.shifted), None, None
+        outs = [adjoint(g[i], w, h, ctx.quads, ctx.shifted) for i in range(g.shape[0])]
+        return torch.stack(outs), None, None
+
+
+def fht(img, quads="full", shifted=False):
+    return FHTFunction.apply(img, quads, shifted)
+
+
+class BatchPlan:
+    """Plan for transforming many images of different sizes in one launch."""
+
+    def __init__(self, sizes, quads="full", in_dtype=torch.uint8, device=None):
+        self.sizes = [(int(h), int(w)) for h, w in sizes]
+        self.n = len(self.sizes)
+        self.quads = _quads(quads)
+        it, at, self.out_dtype = _dtypes(in_dtype)
+        self.in_code, self.acc_code = it, at
+        self.in_dtype = in_dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        ws = (ctypes.c_int32 * self.n)(*[w for h, w in self.sizes])
+        hs = (ctypes.c_int32 * self.n)(*[h for h, w in self.sizes])
+        plan = ctypes.c_void_p()
+        wsb = ctypes.c_size_t()
+        tot = ctypes.c_int64()
+        offs = (ctypes.c_int64 * self.n)()
+        with torch.cuda.device(self.device):
+            _check(lib().fht_batch_plan_create(ws, hs, self.n, self.quads, it, at, ctypes.byref(plan),
+                                               ctypes.byref(wsb), ctypes.byref(tot), offs),
+                   "fht_batch_plan_create")
+        self._plan = plan
+        self.workspace_bytes = wsb.value
+        self.out_elems = tot.value
+        self.offsets = [offs[i] for i in range(self.n)]
+        self.shapes = [hough_shape(w, h, self.quads) for h, w in self.sizes]
+        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+
+    def output(self) -> torch.Tensor:
+        return torch.empty(self.out_elems, dtype=self.out_dtype, device=self.device)
+
+    def views(self, packed: torch.Tensor):
+        return [packed[o:o + r * c].view(r, c) for o, (r, c) in zip(self.offsets, self.shapes)]
+
+    def pointer_table(self, imgs) -> torch.Tensor:
+        for x, (h, w) in zip(imgs, self.sizes):
+            if x.shape != (h, w) or x.dtype != self.in_dtype or not x.is_contiguous() or x.device != self.device:
+                raise ValueError("batch image does not match the plan")
+        return torch.tensor([x.data_ptr() for x in imgs], dtype=torch.int64, device=self.device)
+
+    def run(self, ptr_table: torch.Tensor, packed: torch.Tensor):
+        rc = lib().fht_batch_forward(self._plan, ptr_table.data_ptr(), packed.data_ptr(), self.workspace.data_ptr(),
+                                     self.workspace.numel(), _stream())
+        _check(rc, "fht_batch_forward")
+        return packed
+
+    def __call__(self, imgs):
+        packed = self.output()
+        self.run(self.pointer_table(imgs), packed)
+        return self.views(packed)
+
+    def __del__(self):
+        p = getattr(self, "_plan", None)
+        if p is not None and p.value and _lib is not None:
+            _lib.fht_batch_plan_destroy(p)
+            self._plan = None

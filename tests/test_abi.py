@@ -1,0 +1,127 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1811_06378_amd import fht
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fht.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(fht.LIB_PATH), reason="libfht.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fht_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert "fht_forward" in names and "fht_adjoint" in names and "fht_range" in names and "fht_shift" in names
+    L = fht.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(fht.SIGNATURES), "binding signatures must cover the header exactly"
+
+
+def test_version_and_strings():
+    L = fht.lib()
+    assert L.fht_version() >= 10000
+    for rc in (0, -1, -2, -3, -4, -5):
+        assert L.fht_status_string(rc)
+
+
+@pytest.mark.parametrize("w,h,quads,rows,cols", [
+    (1, 1, 15, 1, 2), (1024, 1024, 15, 4093, 2048), (4096, 4096, 15, 16381, 8192),
+    (100, 37, 15, 2 * (128 + 64) - 3, 192), (100, 37, 1, 64, 192), (100, 37, 4, 128, 192),
+    (100, 37, 5, 192, 192), (100, 37, 14, 64 + 128 + 128, 192)])
+def test_hough_shape(w, h, quads, rows, cols):
+    assert fht.hough_shape(w, h, quads) == (rows, cols)
+
+
+@pytest.mark.parametrize("args", [(0, 5, 15), (5, 0, 15), (5, 5, 0), (5, 5, 16), (70000, 5, 15)])
+def test_hough_shape_rejects(args):
+    with pytest.raises(ValueError):
+        fht.hough_shape(*args)
+
+
+def test_range_shape():
+    assert fht.range_shape(1024, 1024, 275, 550) == (551, 2048)
+    with pytest.raises(ValueError):
+        fht.range_shape(1024, 1024, 275, 1024)
+    with pytest.raises(ValueError):
+        fht.range_shape(1024, 1024, -1024, 5)
+
+
+def test_pass_split():
+    assert fht.pass_split(4096) == [6, 6]
+    assert fht.pass_split(1024) == [5, 5]
+    assert fht.pass_split(256) == [4, 4]
+    assert fht.pass_split(64) == [6]
+    assert fht.pass_split(3) == [2]
+    assert fht.pass_split(8192) == [5, 4, 4]
+    for side in [1, 2, 5, 8, 100, 3000, 65536]:
+        k = max(0, (side - 1).bit_length())
+        assert sum(fht.pass_split(side)) == k
+
+
+def test_workspace_size_monotone():
+    a = fht.workspace_size(1024, 1024)
+    b = fht.workspace_size(4096, 4096)
+    assert 0 < a < b
+    assert fht.workspace_size(64, 64) == 0          # one pass: no intermediate band
+
+
+def test_validation_before_hip():
+    """Invalid calls return a negative status without any HIP call (works on a
+    machine with no GPU)."""
+    L = fht.lib()
+    s = ctypes.c_void_p(0)
+    dummy = ctypes.c_void_p(0x1000)
+    # null image
+    assert L.fht_forward(None, 2, 8, 8, 8, dummy, 2, 16, 15, 0, None, 0, s) == fht.FHT_ERR_INVALID
+    # bad dtype pair
+    assert L.fht_forward(dummy, 0, 8, 8, 8, dummy, 2, 16, 15, 0, None, 0, s) == fht.FHT_ERR_INVALID
+    # pitch too small
+    assert L.fht_forward(dummy, 2, 8, 8, 7, dummy, 2, 16, 15, 0, None, 0, s) == fht.FHT_ERR_INVALID
+    assert L.fht_forward(dummy, 2, 8, 8, 8, dummy, 2, 15, 15, 0, None, 0, s) == fht.FHT_ERR_INVALID
+    # shifted needs the full image
+    assert L.fht_forward(dummy, 2, 8, 8, 8, dummy, 2, 16, 1, 1, None, 0, s) == fht.FHT_ERR_INVALID
+    # workspace missing for a two-pass size
+    assert L.fht_forward(dummy, 2, 1024, 1024, 1024, dummy, 2, 2048, 15, 0, None, 0, s) == fht.FHT_ERR_WORKSPACE
+    assert L.fht_forward(dummy, 2, 1024, 1024, 1024, dummy, 2, 2048, 15, 0, dummy, 16, s) == fht.FHT_ERR_WORKSPACE
+    assert b"workspace" in L.fht_last_error()
+    # range bounds
+    assert L.fht_range(dummy, 0, 64, 64, 64, 0, 64, 0, dummy, 1, 128, None, 0, s) == fht.FHT_ERR_INVALID
+    # adjoint type
+    assert L.fht_adjoint(dummy, 0, 16, dummy, 8, 8, 8, 15, 0, None, 0, s) == fht.FHT_ERR_INVALID
+    # fhtshift overlap that is not identity
+    assert L.fht_shift(dummy, 16, ctypes.c_void_p(0x1004), 16, 2, 8, 8, 0, s) == fht.FHT_ERR_INVALID
+    # batch: bad sizes
+    p = ctypes.c_void_p()
+    wsb, tot = ctypes.c_size_t(), ctypes.c_int64()
+    ws = (ctypes.c_int32 * 2)(8, 0)
+    hs = (ctypes.c_int32 * 2)(8, 8)
+    assert L.fht_batch_plan_create(ws, hs, 2, 15, 0, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
+                                   None) in (fht.FHT_ERR_INVALID, fht.FHT_ERR_UNSUPPORTED)
+
+
+def test_range_params_helper():
+    assert fht.range_params(1024, -15, 15) == (275, 550)
+    assert fht.range_params(1, -15, 15) == (0, 0)
+
+
+def test_product_path_has_no_oracle_import():
+    """The package never imports the oracle (test infrastructure only)."""
+    pkg = os.path.join(ROOT, "paper_1811_06378_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text and "fht_oracle" not in text, f

@@ -1,0 +1,139 @@
+"""Forward parity on the GPU: libfht.so through its C ABI vs the CPU oracle.
+
+Integer images: bit-exact.  Float images: bit-exact against the oracle's
+binary32 mode (same add tree) and within 1e-5 * FHT(|I|) of the float64
+oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_close_fp, assert_equal, dev, host
+from paper_1811_06378_amd import fht
+from paper_1811_06378_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# tiny (direct kernel), one tile, several tiles, ragged tails, non-square, non-pow2
+SIZES = [(1, 1), (2, 3), (3, 2), (4, 4), (5, 13), (8, 8), (16, 16), (9, 40), (64, 64), (33, 100),
+         (128, 128), (129, 257), (300, 520), (520, 300), (1000, 70)]
+
+
+def _img(h, w, kind, seed=0):
+    return synth.random_image(h, w, kind, seed)
+
+
+def _oracle_full(img, single=False):
+    return oracle.full(img.astype(np.float64), single=single)
+
+
+@pytest.mark.parametrize("h,w", SIZES)
+@pytest.mark.parametrize("kind", ["u8", "i32"])
+def test_full_integer_exact(h, w, kind):
+    img = _img(h, w, kind)
+    got = host(fht.forward(dev(img)))
+    assert got.dtype == np.int32
+    assert_equal(got.astype(np.float64), _oracle_full(img), "full %s %dx%d" % (kind, h, w))
+
+
+@pytest.mark.parametrize("h,w", SIZES)
+def test_full_float(h, w):
+    img = _img(h, w, "f32")
+    got = host(fht.forward(dev(img)))
+    assert_equal(got.astype(np.float64), _oracle_full(img, single=True), "full f32 vs binary32 oracle")
+    assert_close_fp(got, _oracle_full(img), _oracle_full(np.abs(img)), "full f32 vs float64 oracle")
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (4, 4), (8, 8), (16, 24), (100, 33), (300, 520)])
+@pytest.mark.parametrize("quads", [[1], [2], [3], [4], [1, 3], [2, 3, 4]])
+def test_quadrant_subsets(h, w, quads):
+    img = _img(h, w, "u8", seed=3)
+    got = host(fht.forward(dev(img), quads=quads))
+    want = oracle.stacked_quadrants(img, quads)
+    assert_equal(got.astype(np.float64), want, "quads %s %dx%d" % (quads, h, w))
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (2, 2), (8, 8), (13, 5), (64, 64), (300, 520)])
+@pytest.mark.parametrize("kind", ["u8", "f32"])
+def test_full_shifted(h, w, kind):
+    img = _img(h, w, kind, seed=5)
+    got = host(fht.forward(dev(img), shifted=True))
+    want = oracle.fhtshift_full(_oracle_full(img, single=(kind == "f32")), w, h)
+    assert_equal(got.astype(np.float64), want, "shifted %s" % kind)
+
+
+@pytest.mark.parametrize("h,w", [(2, 2), (8, 8), (13, 5), (128, 64), (300, 520)])
+@pytest.mark.parametrize("inplace", [False, True])
+def test_shift_kernel(h, w, inplace):
+    img = _img(h, w, "i32", seed=6)
+    H = fht.forward(dev(img))
+    ref = _oracle_full(img)
+    out = H if inplace else None
+    S = fht.shift(H, w, h, out=out)
+    assert_equal(host(S).astype(np.float64), oracle.fhtshift_full(ref, w, h), "fht_shift")
+    back = fht.shift(S, w, h, inverse=True, out=(S if inplace else None))
+    assert_equal(host(back).astype(np.float64), ref, "inverse fht_shift")
+
+
+RANGES = [(8, 8, 0, 7, False), (8, 8, 7, 0, False), (16, 16, 3, 9, False), (16, 20, -5, 10, False),
+          (64, 64, 20, 40, False), (100, 70, -30, 100, False), (256, 256, 68, 136, False),
+          (300, 520, 40, 200, True), (520, 300, -100, 300, False), (4, 4, 1, 2, False), (2, 5, 1, 1, False)]
+
+
+@pytest.mark.parametrize("h,w,S1,S,tr", RANGES)
+@pytest.mark.parametrize("kind", ["u8", "f32"])
+def test_range(h, w, S1, S, tr, kind):
+    img = _img(h, w, kind, seed=8)
+    got = host(fht.range_transform(dev(img), S1, S, transposed=tr))
+    want = oracle.range_transform(img.astype(np.float64), S1, S, transposed=tr, single=(kind == "f32"))
+    assert_equal(got.astype(np.float64), want, "range %dx%d S1=%d S=%d" % (h, w, S1, S))
+
+
+def test_binary256_quadrant1():
+    """256 x 256 binary image, quadrant 1 only, int32: bit-exact vs the oracle
+    and vs brute-force pattern sums on sampled cells."""
+    img = synth.binary256(0)
+    got = host(fht.forward(dev(img), quads=[1]))
+    want = oracle.quadrant(img, 1)
+    assert_equal(got.astype(np.float64), want, "binary256 q1")
+    rng = np.random.default_rng(1)
+    for s, x in zip(rng.integers(0, 256, 50), rng.integers(0, 512, 50)):
+        assert got[s, x] == oracle.cell(img, 1, int(s), int(x))
+
+
+def test_sparse1024_full_shift_range():
+    """1024 x 1024 uint8: full image, fhtshift and the [-15, +15] degree range,
+    all bit-exact."""
+    img = synth.sparse1024(0)
+    x = dev(img)
+    F = _oracle_full(img)
+    assert_equal(host(fht.forward(x)).astype(np.float64), F, "sparse1024 full")
+    assert_equal(host(fht.forward(x, shifted=True)).astype(np.float64), oracle.fhtshift_full(F, 1024, 1024),
+                 "sparse1024 shifted")
+    S1, S = fht.range_params(1024, -15, 15)
+    assert (S1, S) == (275, 550)
+    assert_equal(host(fht.range_transform(x, S1, S)).astype(np.float64),
+                 oracle.range_transform(img, S1, S), "sparse1024 range")
+
+
+def test_repeat_calls_identical():
+    img = _img(300, 520, "f32", seed=9)
+    x = dev(img)
+    a = host(fht.forward(x))
+    b = host(fht.forward(x))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_pitched_buffers():
+    """Image and Hough rows with pitches larger than their widths."""
+    img = _img(77, 90, "i32", seed=10)
+    big = np.zeros((77, 128), dtype=np.int32)
+    big[:, :90] = img
+    x = dev(big)[:, :90]
+    rows, cols = fht.hough_shape(90, 77)
+    out_big = torch.full((rows, cols + 37), -7, dtype=torch.int32, device="cuda")
+    fht.forward(x, out=out_big[:, :cols])
+    got = host(out_big)
+    assert_equal(got[:, :cols].astype(np.float64), _oracle_full(img), "pitched")
+    assert np.all(got[:, cols:] == -7)
