@@ -7,6 +7,7 @@ from .oracle import (  # noqa: F401
     build,
     lib_path,
     next_pow2,
+    threads,
     pattern_offset,
     quadrant,
     full,

@@ -34,6 +34,9 @@
  *                (section 3.3).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -41,6 +44,16 @@
 #define ORACLE_OK 0
 #define ORACLE_BAD_ARG -1
 #define ORACLE_NO_MEMORY -2
+
+/* Threads the OpenMP loops use (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int64_t oracle_next_pow2(int64_t v)
 {

@@ -47,6 +47,8 @@ def _load():
             if not os.path.exists(_LIB):
                 build(force=False)
             lib = ctypes.CDLL(_LIB)
+            lib.oracle_threads.restype = ctypes.c_int
+            lib.oracle_threads.argtypes = []
             lib.oracle_next_pow2.restype = _I64
             lib.oracle_next_pow2.argtypes = [_I64]
             lib.oracle_pattern_offset.restype = _I64
@@ -105,6 +107,11 @@ def _rc(rc: int):
         raise MemoryError("oracle: out of memory")
     if rc != 0:
         raise RuntimeError("oracle: status %d" % rc)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(_load().oracle_threads())
 
 
 def next_pow2(v: int) -> int:

@@ -9,6 +9,7 @@
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace fht {
@@ -79,6 +80,8 @@ QuadGeom quad_geom(int w, int h, int q, int S1)
         const int64_t spread = (int64_t(1) << j) - 1;
         int64_t lo = (S1 < 0 ? S1 : 0) - (g.dir > 0 ? spread : 0);
         int64_t hi = (S1 > 0 ? S1 : 0) + g.other + (g.dir < 0 ? spread : 0);
+        // band origin on a 64-column boundary keeps the tile windows aligned
+        lo = -(((-lo) + 63) / 64) * 64;
         int64_t bw = hi - lo;
         if (bw > g.W) bw = g.W;
         g.band_off[p] = (int)(-lo);
@@ -315,20 +318,44 @@ PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int in_src_ki
 
 // Runs the forward passes of the quadrant geometries gs[0..nq) (all already
 // described by descs[i][p]); one launch per (pass index, fusion depth).
+// Launch order: 0 = pass-major (one launch per pass covers every quadrant),
+// 1 = quadrant-major (a quadrant's passes run back to back, so its band is
+// read again while it is still cached).  FHT_ORDER overrides the default.
+static int launch_order()
+{
+    static int order = -1;
+    if (order < 0) {
+        const char* e = getenv("FHT_ORDER");
+        order = (e && e[0] == '1') ? 1 : 0;
+    }
+    return order;
+}
+
 int run_forward_passes(const QuadGeom* gs, PassDesc (*descs)[4], int nq, int in_t, int acc_t,
                        hipStream_t stream)
 {
+    if (launch_order() == 1 && nq > 1) {
+        for (int i = 0; i < nq; ++i) {
+            int rc = run_forward_passes(&gs[i], &descs[i], 1, in_t, acc_t, stream);
+            if (rc) return rc;
+        }
+        return FHT_OK;
+    }
     int maxp = 0;
     for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
     for (int p = 0; p < maxp; ++p) {
         for (int G = 0; G <= kMaxG; ++G) {
-            PassLaunch L{};
-            for (int i = 0; i < nq; ++i)
-                if (p < gs[i].npass && gs[i].G[p] == G) L.d[L.nd++] = descs[i][p];
-            if (L.nd == 0) continue;
-            const int ti = p == 0 ? in_t : acc_t;
-            hipError_t e = G <= 2 ? launch_direct(L, G, ti, acc_t, stream) : launch_pass(L, G, ti, acc_t, stream);
-            if (e != hipSuccess) return hip_fail(e, "forward pass launch");
+            for (int last = 0; last < 2; ++last) {
+                PassLaunch L{};
+                for (int i = 0; i < nq; ++i)
+                    if (p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (last != 0))
+                        L.d[L.nd++] = descs[i][p];
+                if (L.nd == 0) continue;
+                const int ti = p == 0 ? in_t : acc_t;
+                hipError_t e = G <= 2 ? launch_direct(L, G, ti, acc_t, stream)
+                                      : launch_pass(L, G, p == 0, last != 0, ti, acc_t, stream);
+                if (e != hipSuccess) return hip_fail(e, "forward pass launch");
+            }
         }
     }
     return FHT_OK;
@@ -517,12 +544,15 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     for (int p = maxp - 1; p >= 0; --p) {
         if (p > 0) {
             for (int G = 3; G <= kMaxG; ++G) {
-                AdjLaunch L{};
-                for (int i = 0; i < nq; ++i)
-                    if (p < gs[i].npass && gs[i].G[p] == G) L.d[L.nd++] = descs[i][p];
-                if (L.nd == 0) continue;
-                hipError_t e = launch_adjoint_pass(L, G, t, s);
-                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+                for (int first = 0; first < 2; ++first) {
+                    AdjLaunch L{};
+                    for (int i = 0; i < nq; ++i)
+                        if (p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first != 0))
+                            L.d[L.nd++] = descs[i][p];
+                    if (L.nd == 0) continue;
+                    hipError_t e = launch_adjoint_pass(L, G, first != 0, false, t, s);
+                    if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+                }
             }
         } else {
             for (int i = 0; i < nq; ++i) {
@@ -530,7 +560,8 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 L.d[0] = descs[i][0];
                 L.nd = 1;
                 const int G = gs[i].G[0];
-                hipError_t e = G <= 2 ? launch_adjoint_direct(L, G, t, s) : launch_adjoint_pass(L, G, t, s);
+                hipError_t e = G <= 2 ? launch_adjoint_direct(L, G, t, s)
+                                      : launch_adjoint_pass(L, G, gs[i].npass == 1, true, t, s);
                 if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
             }
         }

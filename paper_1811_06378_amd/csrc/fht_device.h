@@ -85,6 +85,10 @@ template <typename T> __device__ __forceinline__ T to_acc(float v) { return (T)v
 // Forward stage J on 8 register rows: blocks of 2^(J+1) rows, block rows
 // t = 0..2^(J+1)-1 from rows (t>>1) and 2^J + (t>>1), the latter shifted by
 // dir*(t - (t>>1)) columns.
+// Forward stage J on 8 register rows: blocks of 2^(J+1) rows; block rows
+// 2i and 2i+1 both come from the pair (top row i, bottom row 2^J + i), the
+// bottom one shifted by dir*i and dir*(i+1) columns.  Each output pair
+// depends on one input pair only, so the stage is a set of row butterflies.
 template <typename T, int DIR, int J>
 __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
 {
@@ -93,17 +97,21 @@ __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
 #pragma unroll
     for (int blk = 0; blk < 8; blk += 2 * H) {
 #pragma unroll
-        for (int t = 0; t < 2 * H; ++t) {
-            const int sub = t >> 1;
-            const int d = t - sub;
+        for (int i = 0; i < H; ++i) {
+            const T (&top)[8] = a[blk + i];
+            const T (&bot)[8] = a[blk + H + i];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const int cc = c + DIR * d;
-                T bot;
-                if (cc >= 8) bot = dpp_move<kDppFromNext>(a[blk + H + sub][cc - 8]);
-                else if (cc < 0) bot = dpp_move<kDppFromPrev>(a[blk + H + sub][cc + 8]);
-                else bot = a[blk + H + sub][cc];
-                o[blk + t][c] = a[blk + sub][c] + bot;
+                int c0 = c + DIR * i, c1 = c + DIR * (i + 1);
+                T b0, b1;
+                if (c0 >= 8) b0 = dpp_move<kDppFromNext>(bot[c0 - 8]);
+                else if (c0 < 0) b0 = dpp_move<kDppFromPrev>(bot[c0 + 8]);
+                else b0 = bot[c0];
+                if (c1 >= 8) b1 = dpp_move<kDppFromNext>(bot[c1 - 8]);
+                else if (c1 < 0) b1 = dpp_move<kDppFromPrev>(bot[c1 + 8]);
+                else b1 = bot[c1];
+                o[blk + 2 * i][c] = top[c] + b0;
+                o[blk + 2 * i + 1][c] = top[c] + b1;
             }
         }
     }
@@ -172,6 +180,58 @@ __device__ __forceinline__ void adj_stages_b(T (&b)[8][8])
     if constexpr (GB > 0) adj_stage<T, DIR, 0>(b);
 }
 
+// LDS rows are column-swizzled: column x lives in plane (x & 7) at slot
+// (x >> 3), so lane-contiguous 8-column groups and offset reads both spread
+// over all banks.  A row segment starting at a wave-uniform offset is
+// accessed through one base address plus compile-time immediates: the
+// residue (off & 7) selects one of 8 unrolled patterns.
+template <int O7, typename T>
+__device__ __forceinline__ void lds_read8_fixed(const T* p, T (&v)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = p[((c + O7) & 7) * kPlane + ((c + O7) >> 3)];
+}
+
+template <int O7, typename T>
+__device__ __forceinline__ void lds_write8_fixed(T* p, const T (&v)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) p[((c + O7) & 7) * kPlane + ((c + O7) >> 3)] = v[c];
+}
+
+// row_lane = row base + lane; off >= 0 (wave-uniform)
+template <typename T>
+__device__ __forceinline__ void lds_read8(const T* row_lane, int off, T (&v)[8])
+{
+    const T* p = row_lane + (off >> 3);
+    switch (off & 7) {
+    case 0: lds_read8_fixed<0>(p, v); break;
+    case 1: lds_read8_fixed<1>(p, v); break;
+    case 2: lds_read8_fixed<2>(p, v); break;
+    case 3: lds_read8_fixed<3>(p, v); break;
+    case 4: lds_read8_fixed<4>(p, v); break;
+    case 5: lds_read8_fixed<5>(p, v); break;
+    case 6: lds_read8_fixed<6>(p, v); break;
+    default: lds_read8_fixed<7>(p, v); break;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_write8(T* row_lane, int off, const T (&v)[8])
+{
+    T* p = row_lane + (off >> 3);
+    switch (off & 7) {
+    case 0: lds_write8_fixed<0>(p, v); break;
+    case 1: lds_write8_fixed<1>(p, v); break;
+    case 2: lds_write8_fixed<2>(p, v); break;
+    case 3: lds_write8_fixed<3>(p, v); break;
+    case 4: lds_write8_fixed<4>(p, v); break;
+    case 5: lds_write8_fixed<5>(p, v); break;
+    case 6: lds_write8_fixed<6>(p, v); break;
+    default: lds_write8_fixed<7>(p, v); break;
+    }
+}
+
 __device__ __forceinline__ int lds_index(int tile_row, int col)
 {
     // column-swizzled: column col of a row lives in plane (col & 7) at (col >> 3),
@@ -179,48 +239,230 @@ __device__ __forceinline__ int lds_index(int tile_row, int col)
     return tile_row * kLdsRow + (col & 7) * kPlane + (col >> 3);
 }
 
-// ------------------------------------------------------------ source loads
+// ------------------------------------------------------------ vector access
 
-// Padded source value at quadrant row R, for the 8 columns owned by this lane
-// starting at logical column x (any integer; taken mod W).
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef int i32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef unsigned int u32x2u __attribute__((ext_vector_type(2), aligned(4)));
+
+template <typename T> struct vec4u;
+template <> struct vec4u<float> { typedef f32x4u type; };
+template <> struct vec4u<int> { typedef i32x4u type; };
+
+// 8 consecutive elements.  Only dword alignment is required: gfx950 serves
+// dword-aligned 16-byte vector accesses, which the pre-rolled rows need.
+template <typename T>
+__device__ __forceinline__ void load8(const T* p, T (&v)[8])
+{
+    typedef typename vec4u<T>::type V;
+    const V a = *reinterpret_cast<const V*>(p);
+    const V b = *reinterpret_cast<const V*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+template <typename T>
+__device__ __forceinline__ void store8(T* p, const T (&v)[8])
+{
+    typedef typename vec4u<T>::type V;
+    V a, b;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
+    *reinterpret_cast<V*>(p) = a;
+    *reinterpret_cast<V*>(p + 4) = b;
+}
+
+// Streaming store for the final Hough image (written once, never re-read here).
+template <typename T>
+__device__ __forceinline__ void store8_stream(T* p, const T (&v)[8])
+{
+    typedef typename vec4u<T>::type V;
+    V a, b;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
+    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<V*>(p + 4));
+}
+
+template <typename TIn>
+__device__ __forceinline__ bool vec_ok(const TIn* p)
+{
+    if constexpr (sizeof(TIn) == 1) return (reinterpret_cast<uintptr_t>(p) & 3) == 0;
+    else return true;
+}
+
 template <typename TIn, typename T>
-__device__ __forceinline__ void load_row(const PassDesc& d, int R, long long x, T (&v)[8])
+__device__ __forceinline__ void load8_src(const TIn* p, T (&v)[8])
+{
+    if constexpr (sizeof(TIn) == 1) {
+        const u32x2u w = *reinterpret_cast<const u32x2u*>(p);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            v[c] = (T)((w.x >> (8 * c)) & 0xFFu);
+            v[4 + c] = (T)((w.y >> (8 * c)) & 0xFFu);
+        }
+    } else {
+        load8<T>(reinterpret_cast<const T*>(p), v);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero8(T (&v)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = (T)0;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// a mod W for a wave-uniform a (the pass geometry keeps |a| < 4W whenever
+// W >= 1024; small W takes the division).
+__device__ __forceinline__ int mod_w(int a, int W)
+{
+    if (W >= 1024 && a > -4 * W && a < 4 * W) {
+        a += 4 * W;
+        if (a >= 4 * W) a -= 4 * W;
+        if (a >= 2 * W) a -= 2 * W;
+        if (a >= W) a -= W;
+        return a;
+    }
+    int r = a % W;
+    return r < 0 ? r + W : r;
+}
+
+// e in [0, W + 512) -> e mod W
+__device__ __forceinline__ int wrap_lane(int e, int W)
+{
+    if (e >= W) e -= W;
+    if (e >= W) e %= W;
+    return e;
+}
+
+// ------------------------------------------------------------ source loads
+//
+// Loads are issued for all rows before any result is used: lanes whose 8
+// columns lie inside the data read them with two 16-byte loads, lanes whose 8
+// columns are all zero padding read a static zero page, and only lanes that
+// straddle a boundary (rare) are patched element by element afterwards.  An
+// if/else per row would make every row wait for the previous row's loads.
+
+static __device__ __attribute__((aligned(64))) unsigned int g_zero_page[16];
+
+template <typename T>
+__device__ __forceinline__ const T* zero_page()
+{
+    return reinterpret_cast<const T*>(g_zero_page);
+}
+
+// Band row R: returns the lane's first band index and whether it needs a patch.
+template <typename T>
+__device__ __forceinline__ bool issue_band_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
 {
     const int W = d.W;
-    if (d.src_kind == SRC_BAND) {
-        const T* band = reinterpret_cast<const T*>(d.src) + (long long)R * d.src_ld;
-        int e0 = mod_pos(x + d.src_off, W);
+    const T* band = reinterpret_cast<const T*>(d.src) + (long long)R * d.src_ld;
+    e0 = wrap_lane(mod_w(xrow + d.src_off, W) + 8 * lane, W);
+    const bool fast = e0 + 8 <= d.src_bw;
+    const bool zero = e0 >= d.src_bw && e0 + 8 <= W;
+    load8<T>(fast ? band + e0 : zero_page<T>(), v);
+    return !fast && !zero;
+}
+
+template <typename T>
+__device__ __forceinline__ void patch_band_row(const PassDesc& d, int R, int e0, T (&v)[8])
+{
+    const int W = d.W;
+    const T* band = reinterpret_cast<const T*>(d.src) + (long long)R * d.src_ld;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int e = wrap_once(e0 + c, W);
-            v[c] = (e < d.src_bw) ? band[e] : (T)0;
-        }
-        return;
+    for (int c = 0; c < 8; ++c) {
+        int e = e0 + c;
+        if (e >= W) e -= W;
+        v[c] = (e < d.src_bw) ? band[e] : (T)0;
     }
+}
+
+// Image row R (quadrants 1, 2; sheared for the angle range).
+template <typename TIn, typename T>
+__device__ __forceinline__ bool issue_image_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
+{
+    const int W = d.W;
+    const TIn* p = reinterpret_cast<const TIn*>(d.src) + (long long)R * d.src_ld;
+    e0 = wrap_lane(mod_w(xrow - shear_of_row(R, d.S1, d.n), W) + 8 * lane, W);
+    const bool row_ok = R < d.img_h;
+    const bool fast = row_ok && e0 + 8 <= d.img_w && vec_ok<TIn>(p + e0);
+    const bool zero = !row_ok || (e0 >= d.img_w && e0 + 8 <= W);
+    load8_src<TIn, T>(fast ? p + e0 : zero_page<TIn>(), v);
+    return !fast && !zero;
+}
+
+template <typename TIn, typename T>
+__device__ __forceinline__ void patch_image_row(const PassDesc& d, int R, int e0, T (&v)[8])
+{
+    const int W = d.W;
     const TIn* img = reinterpret_cast<const TIn*>(d.src);
-    const int sh = shear_of_row(R, d.S1, d.n);
-    int e0 = mod_pos(x - sh, W);
-    if (d.src_kind == SRC_IMAGE) {
-        const bool row_ok = R < d.img_h;
-        const TIn* p = img + (long long)R * d.src_ld;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        int e = e0 + c;
+        if (e >= W) e -= W;
+        if (d.src_kind == SRC_IMAGE)
+            v[c] = (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + e]) : (T)0;
+        else
+            v[c] = (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)e * d.src_ld + R]) : (T)0;
+    }
+}
+
+// Transposed image (quadrants 3, 4) with a shear: element loads only.
+template <typename TIn, typename T>
+__device__ __forceinline__ bool issue_image_t_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
+{
+    e0 = wrap_lane(mod_w(xrow - shear_of_row(R, d.S1, d.n), d.W) + 8 * lane, d.W);
+    zero8(v);
+    return true;
+}
+
+// Rows R0..R0+7 of the transposed image (image columns), unsheared: for each
+// of the lane's 8 columns (image rows) the 8 values are contiguous in memory.
+template <typename TIn, typename T>
+__device__ __forceinline__ void load_rows_transposed(const PassDesc& d, int R0, int xrow, int lane, T (&a)[8][8])
+{
+    const int W = d.W;
+    const int e0 = wrap_lane(mod_w(xrow, W) + 8 * lane, W);
+    const TIn* img = reinterpret_cast<const TIn*>(d.src);
+    const bool all_cols = R0 + 8 <= d.img_w;
+    T t[8][8];
+    bool patch[8];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        int e = e0 + c;
+        if (e >= W) e -= W;
+        const TIn* p = img + (long long)e * d.src_ld + R0;
+        const bool inside = e < d.img_h;
+        const bool fast = inside && all_cols && vec_ok<TIn>(p);
+        load8_src<TIn, T>(fast ? p : zero_page<TIn>(), t[c]);
+        patch[c] = inside && !fast;
+        any |= patch[c];
+    }
+    if (__any(any)) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            int e = wrap_once(e0 + c, W);
-            v[c] = (row_ok && e < d.img_w) ? to_acc<T>(p[e]) : (T)0;
-        }
-    } else {  // SRC_IMAGE_T: quadrant row R is image column R
-        const bool col_ok = R < d.img_w;
+            if (patch[c]) {
+                int e = e0 + c;
+                if (e >= W) e -= W;
+                const TIn* p = img + (long long)e * d.src_ld + R0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int e = wrap_once(e0 + c, W);
-            v[c] = (col_ok && e < d.img_h) ? to_acc<T>(img[(long long)e * d.src_ld + R]) : (T)0;
+                for (int r = 0; r < 8; ++r) t[c][r] = (R0 + r < d.img_w) ? to_acc<T>(p[r]) : (T)0;
+            }
         }
     }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r][c] = t[c][r];
 }
 
 // ------------------------------------------------------ fused forward pass
 
-template <typename TIn, typename T, int GB, int DIR>
+template <typename TIn, typename T, int GB, int DIR, bool FIRST, bool LAST>
 __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* lds)
 {
     constexpr int G = 3 + GB;
@@ -228,53 +470,97 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
     constexpr int VW = kWinCols - (1 << G);      // stored columns per tile
     constexpr int LOFF = DIR > 0 ? 0 : kLdsOffNeg;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform(threadIdx.x >> 6);
     const int j0 = d.j0;
     const int n_mini = d.n >> G;
-    const long long x_lo = (long long)d.x_start + (long long)win * VW;
-    const long long xw0 = x_lo - (DIR < 0 ? (1 << G) : 0);
+    const int x_lo = d.x_start + win * VW;
+    const int xw0 = x_lo - (DIR < 0 ? (1 << G) : 0);
 
     // ---- phase A: 8 contiguous mini rows per wave, first 3 stages
     T a[8][8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int tr = wave * 8 + r;
-        const int t = tr >> G;
-        const int m = tr & ((1 << G) - 1);
+    {
+        const int tr0 = wave * 8;
+        const int t = tr0 >> G;
         const int mu = rt * NMINI + t;
         const int B = mu >> j0;
         const int u = mu & ((1 << j0) - 1);
         const bool active = (mu < n_mini) && ((u << G) <= d.row_limit);
-        if (active) {
-            const int R = (B << (j0 + G)) + (m << j0) + u;
-            load_row<TIn, T>(d, R, xw0 + 8 * lane + (long long)DIR * u * m, a[r]);
-        } else {
+        if (!active) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) a[r][c] = (T)0;
+            for (int r = 0; r < 8; ++r) zero8(a[r]);
+        } else if (FIRST && d.src_kind == SRC_IMAGE_T && d.S1 == 0) {
+            // first pass (u = 0): the wave's rows are 8 consecutive image columns
+            load_rows_transposed<TIn, T>(d, (B << G) + (tr0 & ((1 << G) - 1)), xw0, lane, a);
+        } else {
+            int e0[8];
+            bool patch[8];
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int m = (tr0 + r) & ((1 << G) - 1);
+                const int R = (B << (j0 + G)) + (m << j0) + u;
+                if constexpr (FIRST) {
+                    patch[r] = d.src_kind == SRC_IMAGE ? issue_image_row<TIn, T>(d, R, xw0, lane, a[r], e0[r])
+                                                       : issue_image_t_row<TIn, T>(d, R, xw0, lane, a[r], e0[r]);
+                } else {
+                    patch[r] = issue_band_row<T>(d, R, xw0 + DIR * u * m, lane, a[r], e0[r]);
+                }
+                any |= patch[r];
+            }
+            if (__any(any)) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    if (patch[r]) {
+                        const int m = (tr0 + r) & ((1 << G) - 1);
+                        const int R = (B << (j0 + G)) + (m << j0) + u;
+                        if constexpr (FIRST) patch_image_row<TIn, T>(d, R, e0[r], a[r]);
+                        else patch_band_row<T>(d, R, e0[r], a[r]);
+                    }
+                }
+            }
         }
     }
     fwd_stage<T, DIR, 0>(a);
     fwd_stage<T, DIR, 1>(a);
     fwd_stage<T, DIR, 2>(a);
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) lds[lds_index(wave * 8 + r, 8 * lane + c + LOFF)] = a[r][c];
-    __syncthreads();
 
-    // ---- phase B: rows 8g + u' with offsets dir*u'*g, last GB stages
+    // ---- phase B: rows 8g + u' with offsets dir*u'*g, last GB stages.  The
+    // exchange runs in two halves (registers 0-3, then 4-7 of every wave) so
+    // the LDS holds 32 rows and two workgroups fit on a CU.
     T b[8][8];
+    if constexpr (GB == 0) {
 #pragma unroll
-    for (int rho = 0; rho < 8; ++rho) {
-        const int rp = rho & ((1 << GB) - 1);
-        const int q = rho >> GB;
-        const int kappa = (wave << (3 - GB)) + q;
-        const int t = kappa >> 3;
-        const int up = kappa & 7;
-        const int tr = (t << G) + (rp << 3) + up;
-        const int off = DIR * up * rp + LOFF;
+        for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) b[rho][c] = lds[lds_index(tr, 8 * lane + c + off)];
+            for (int c = 0; c < 8; ++c) b[r][c] = a[r][c];
+    } else {
+        const int my_half = ((wave << (3 - GB)) & 7) >> 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            {
+                // column 8*lane + c + LOFF of LDS row wave*4 + rr: plane c, slot lane + LOFF/8
+                T* lw = lds + wave * 4 * kLdsRow + lane + LOFF / 8;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) lw[rr * kLdsRow + c * kPlane] = a[4 * h + rr][c];
+            }
+            __syncthreads();
+            if (my_half == h) {
+#pragma unroll
+                for (int rho = 0; rho < 8; ++rho) {
+                    const int rp = rho & ((1 << GB) - 1);
+                    const int q = rho >> GB;
+                    const int kappa = (wave << (3 - GB)) + q;
+                    const int t = kappa >> 3;
+                    const int up = kappa & 7;
+                    const int wa = (t << GB) + rp;         // phase-A wave holding the row
+                    const int off = uniform(DIR * up * rp + LOFF);
+                    lds_read8<T>(lds + (wa * 4 + (up & 3)) * kLdsRow + lane, off, b[rho]);
+                }
+            }
+            if (h == 0) __syncthreads();
+        }
     }
     fwd_stages_b<T, DIR, GB>(b);
 
@@ -282,7 +568,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
     const int wc0 = 8 * lane;
     const bool lane_ok = DIR > 0 ? (wc0 < VW) : (wc0 >= (1 << G));
     if (!lane_ok) return;
-    const long long x0 = xw0 + wc0;
+    const int x0 = xw0 + wc0;
 #pragma unroll
     for (int rho = 0; rho < 8; ++rho) {
         const int rp = rho & ((1 << GB) - 1);
@@ -297,34 +583,48 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         const int s_local = (u << G) + (up << GB) + rp;
         if (s_local > d.row_limit) continue;
         const int out_row = (B << (j0 + G)) + s_local;
-        if (d.dst_kind == DST_BAND) {
+        if constexpr (!LAST) {
             T* dst = reinterpret_cast<T*>(d.dst) + (long long)out_row * d.dst_ld;
-            const long long e0 = x0 + d.dst_off;
+            const int e0 = x0 + d.dst_off;
+            if (e0 + 8 <= d.dst_bw) {
+                store8<T>(dst + e0, b[rho]);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (e0 + c < d.dst_bw) dst[e0 + c] = b[rho][c];
+                for (int c = 0; c < 8; ++c)
+                    if (e0 + c < d.dst_bw) dst[e0 + c] = b[rho][c];
+            }
         } else {
             const int s = out_row;
             if (s == d.skip_row) continue;
             T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
             const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
+            const int W = d.W;
+            if (x0 >= W) continue;
+            const int xr = wrap_lane(x0 + roll, W);
+            if (x0 + 8 <= W && xr + 8 <= W) {
+                store8_stream<T>(dst + xr, b[rho]);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const long long x = x0 + c;
-                if (x < d.W) dst[wrap_once((int)x + roll, d.W)] = b[rho][c];
+                for (int c = 0; c < 8; ++c) {
+                    if (x0 + c < W) {
+                        int e = xr + c;
+                        if (e >= W) e -= W;
+                        dst[e] = b[rho][c];
+                    }
+                }
             }
         }
     }
 }
 
-template <typename TIn, typename T, int GB>
-__global__ __launch_bounds__(kThreads) void fht_pass_kernel(const PassLaunch L)
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch L)
 {
-    __shared__ T lds[kTileRows * kLdsRow];
+    __shared__ T lds[kTileRows / 2 * kLdsRow];
     const PassDesc& d = L.d[blockIdx.z];
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
-    if (d.dir > 0) fwd_tile<TIn, T, GB, 1>(d, blockIdx.y, blockIdx.x, lds);
-    else fwd_tile<TIn, T, GB, -1>(d, blockIdx.y, blockIdx.x, lds);
+    if (d.dir > 0) fwd_tile<TIn, T, GB, 1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
+    else fwd_tile<TIn, T, GB, -1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
 }
 
 // -------------------------------------------- direct form for n <= 4 rows
@@ -376,34 +676,69 @@ __global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
 // the first 3 stages transposed) and row m is written with its column offset
 // dir*u*m added.
 
-template <typename T>
-__device__ __forceinline__ void adj_load_row(const AdjDesc& d, int s_row, long long x, T (&v)[8])
+// Source row of an adjoint pass (Hough gradient or band), issue + patch as
+// for the forward loads.
+template <typename T, bool FROM_HOUGH>
+__device__ __forceinline__ bool adj_issue_row(const AdjDesc& d, int s_row, int xrow, int lane, T (&v)[8], int& e0)
 {
     const int W = d.W;
-    if (d.src_kind == 1) {  // band
+    if constexpr (!FROM_HOUGH) {
         const T* band = reinterpret_cast<const T*>(d.src) + (long long)s_row * d.src_ld;
-        int e0 = mod_pos(x + d.src_off, W);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int e = wrap_once(e0 + c, W);
-            v[c] = (e < d.src_bw) ? band[e] : (T)0;
-        }
-        return;
+        e0 = wrap_lane(mod_w(xrow + d.src_off, W) + 8 * lane, W);
+        const bool fast = e0 + 8 <= d.src_bw;
+        const bool zero = e0 >= d.src_bw && e0 + 8 <= W;
+        load8<T>(fast ? band + e0 : zero_page<T>(), v);
+        return !fast && !zero;
+    } else {
+        const bool skip = s_row == d.skip_row;
+        const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
+        const int roll = d.shifted ? ((d.roll_a + d.roll_b * s_row) >> 1) : 0;
+        e0 = wrap_lane(mod_w(xrow + roll, W) + 8 * lane, W);
+        const bool fast = !skip && e0 + 8 <= W;
+        load8<T>(fast ? src + e0 : zero_page<T>(), v);
+        return !skip && !fast;
     }
-    // Hough gradient: quadrant row s -> Hough row, shifted columns
-    if (s_row == d.skip_row) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = (T)0;
-        return;
-    }
-    const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
-    const int roll = d.shifted ? ((d.roll_a + d.roll_b * s_row) >> 1) : 0;
-    int e0 = mod_pos(x + roll, W);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = src[wrap_once(e0 + c, W)];
 }
 
-template <typename T, int GB, int DIR>
+template <typename T, bool FROM_HOUGH>
+__device__ __forceinline__ void adj_patch_row(const AdjDesc& d, int s_row, int e0, T (&v)[8])
+{
+    const int W = d.W;
+    if constexpr (!FROM_HOUGH) {
+        const T* band = reinterpret_cast<const T*>(d.src) + (long long)s_row * d.src_ld;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int e = e0 + c;
+            if (e >= W) e -= W;
+            v[c] = (e < d.src_bw) ? band[e] : (T)0;
+        }
+    } else {
+        const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int e = e0 + c;
+            if (e >= W) e -= W;
+            v[c] = src[e];
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void acc_store8(T* p, const T (&v)[8], bool accumulate)
+{
+    if (accumulate) {
+        T o[8];
+        load8<T>(p, o);
+        T s[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s[c] = o[c] + v[c];
+        store8<T>(p, s);
+    } else {
+        store8<T>(p, v);
+    }
+}
+
+template <typename T, int GB, int DIR, bool FIRST, bool LAST>
 __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* lds)
 {
     constexpr int G = 3 + GB;
@@ -412,52 +747,93 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
     // transposed shifts point the other way, so the halo sits on the other side
     constexpr int LOFF = DIR > 0 ? 0 : kLdsOffNeg;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform(threadIdx.x >> 6);
     const int j0 = d.j0;
     const int n_mini = d.n >> G;
-    const long long x_lo = (long long)d.x_start + (long long)win * VW;
-    const long long xw0 = x_lo - (DIR > 0 ? (1 << G) : 0);
+    const int x_lo = d.x_start + win * VW;
+    const int xw0 = x_lo - (DIR > 0 ? (1 << G) : 0);
 
     // ---- load the forward pass's output rows (contiguous within a block)
     T b[8][8];
+    {
+        int e0[8];
+        bool patch[8];
+        bool any = false;
 #pragma unroll
-    for (int rho = 0; rho < 8; ++rho) {
-        const int rp = rho & ((1 << GB) - 1);
-        const int q = rho >> GB;
-        const int kappa = (wave << (3 - GB)) + q;
-        const int t = kappa >> 3;
-        const int up = kappa & 7;
-        const int mu = rt * NMINI + t;
-        if (mu < n_mini) {
-            const int B = mu >> j0;
-            const int u = mu & ((1 << j0) - 1);
-            const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
-            adj_load_row<T>(d, s_row, xw0 + 8 * lane, b[rho]);
-        } else {
+        for (int rho = 0; rho < 8; ++rho) {
+            const int rp = rho & ((1 << GB) - 1);
+            const int q = rho >> GB;
+            const int kappa = (wave << (3 - GB)) + q;
+            const int t = kappa >> 3;
+            const int up = kappa & 7;
+            const int mu = rt * NMINI + t;
+            if (mu < n_mini) {
+                const int B = mu >> j0;
+                const int u = mu & ((1 << j0) - 1);
+                const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
+                patch[rho] = adj_issue_row<T, FIRST>(d, s_row, xw0, lane, b[rho], e0[rho]);
+            } else {
+                zero8(b[rho]);
+                patch[rho] = false;
+                e0[rho] = 0;
+            }
+            any |= patch[rho];
+        }
+        if (__any(any)) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) b[rho][c] = (T)0;
+            for (int rho = 0; rho < 8; ++rho) {
+                if (patch[rho]) {
+                    const int rp = rho & ((1 << GB) - 1);
+                    const int q = rho >> GB;
+                    const int kappa = (wave << (3 - GB)) + q;
+                    const int t = kappa >> 3;
+                    const int up = kappa & 7;
+                    const int mu = rt * NMINI + t;
+                    const int B = mu >> j0;
+                    const int u = mu & ((1 << j0) - 1);
+                    const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
+                    adj_patch_row<T, FIRST>(d, s_row, e0[rho], b[rho]);
+                }
+            }
         }
     }
     adj_stages_b<T, DIR, GB>(b);
-#pragma unroll
-    for (int rho = 0; rho < 8; ++rho) {
-        const int rp = rho & ((1 << GB) - 1);
-        const int q = rho >> GB;
-        const int kappa = (wave << (3 - GB)) + q;
-        const int t = kappa >> 3;
-        const int up = kappa & 7;
-        const int tr = (t << G) + (rp << 3) + up;
-        const int off = DIR * up * rp + LOFF;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) lds[lds_index(tr, 8 * lane + c + off)] = b[rho][c];
-    }
-    __syncthreads();
 
+    // ---- exchange (two halves of LDS rows, as in the forward pass)
     T a[8][8];
+    if constexpr (GB == 0) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+        for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) a[r][c] = lds[lds_index(wave * 8 + r, 8 * lane + c + LOFF)];
+            for (int c = 0; c < 8; ++c) a[r][c] = b[r][c];
+    } else {
+        const int my_half = ((wave << (3 - GB)) & 7) >> 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (my_half == h) {
+#pragma unroll
+                for (int rho = 0; rho < 8; ++rho) {
+                    const int rp = rho & ((1 << GB) - 1);
+                    const int q = rho >> GB;
+                    const int kappa = (wave << (3 - GB)) + q;
+                    const int t = kappa >> 3;
+                    const int up = kappa & 7;
+                    const int wa = (t << GB) + rp;
+                    const int off = uniform(DIR * up * rp + LOFF);
+                    lds_write8<T>(lds + (wa * 4 + (up & 3)) * kLdsRow + lane, off, b[rho]);
+                }
+            }
+            __syncthreads();
+            {
+                const T* lr = lds + wave * 4 * kLdsRow + lane + LOFF / 8;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) a[4 * h + rr][c] = lr[rr * kLdsRow + c * kPlane];
+            }
+            if (h == 0) __syncthreads();
+        }
+    }
     adj_stage<T, DIR, 2>(a);
     adj_stage<T, DIR, 1>(a);
     adj_stage<T, DIR, 0>(a);
@@ -466,60 +842,83 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
     const int wc0 = 8 * lane;
     const bool lane_ok = DIR > 0 ? (wc0 >= (1 << G)) : (wc0 < VW);
     if (!lane_ok) return;
-    const long long x0 = xw0 + wc0;  // logical column of register 0 before the offset
+    const int x0 = xw0 + wc0;  // window column of register 0 (before the offset)
+    const int W = d.W;
+    const int tr0 = wave * 8;
+    const int t = tr0 >> G;
+    const int mu = rt * NMINI + t;
+    if (mu >= n_mini) return;
+    const int B = mu >> j0;
+    const int u = mu & ((1 << j0) - 1);
+    if constexpr (!LAST) {
+        // band: window columns [0, W) are covered once; column z of row m lands
+        // on z + dir*u*m, a bijection of the cyclic row
+        if (x0 >= W) return;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int tr = wave * 8 + r;
-        const int t = tr >> G;
-        const int m = tr & ((1 << G) - 1);
-        const int mu = rt * NMINI + t;
-        if (mu >= n_mini) continue;
-        const int B = mu >> j0;
-        const int u = mu & ((1 << j0) - 1);
-        const int R = (B << (j0 + G)) + (m << j0) + u;
-        const long long xo = x0 + (long long)DIR * u * m;
-        if (d.dst_kind == 0) {
-            // band: window columns are band positions x_lo..; the offset moves them
+        for (int r = 0; r < 8; ++r) {
+            const int m = (tr0 + r) & ((1 << G) - 1);
+            const int R = (B << (j0 + G)) + (m << j0) + u;
             T* dst = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld;
-            // the windows cover window columns [0, W) once; column z of row m
-            // lands on z + dir*u*m, a bijection of the cyclic row
-            const int e0 = mod_pos(xo + d.dst_off, d.W);
+            const int e0 = wrap_lane(mod_w(xw0 + DIR * u * m + d.dst_off, W) + wc0, W);
+            if (x0 + 8 <= W && e0 + 8 <= d.dst_bw) {
+                store8<T>(dst + e0, a[r]);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if (x0 + c < (long long)d.W) {
-                    const int e = wrap_once(e0 + c, d.W);
-                    if (e < d.dst_bw) dst[e] = a[r][c];
+                for (int c = 0; c < 8; ++c) {
+                    if (x0 + c < W) {
+                        int e = e0 + c;
+                        if (e >= W) e -= W;
+                        if (e < d.dst_bw) dst[e] = a[r][c];
+                    }
                 }
             }
-        } else {
-            // image: the first forward pass has u = 0, so no offset remains
+        }
+    } else if (d.dst_kind == 1) {
+        // image rows (the first forward pass has u = 0: no offset remains)
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const long long x = x0 + c;
-                if (d.dst_kind == 1) {
-                    if (R < d.img_h && x >= 0 && x < d.img_w) {
-                        T* p = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x;
-                        *p = d.accumulate ? (T)(*p + a[r][c]) : a[r][c];
-                    }
-                } else {
-                    if (R < d.img_w && x >= 0 && x < d.img_h) {
-                        T* p = reinterpret_cast<T*>(d.dst) + (long long)x * d.dst_ld + R;
-                        *p = d.accumulate ? (T)(*p + a[r][c]) : a[r][c];
-                    }
-                }
+        for (int r = 0; r < 8; ++r) {
+            const int R = (B << G) + ((tr0 + r) & ((1 << G) - 1));
+            if (R >= d.img_h || x0 >= d.img_w) continue;
+            T* p = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x0;
+            if (x0 + 8 <= d.img_w) {
+                acc_store8<T>(p, a[r], d.accumulate != 0);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (x0 + c < d.img_w) p[c] = d.accumulate ? (T)(p[c] + a[r][c]) : a[r][c];
+            }
+        }
+    } else {
+        // transposed image: rows R0..R0+7 are image columns, contiguous in memory
+        const int R0 = (B << G) + (tr0 & ((1 << G) - 1));
+        const bool all_cols = R0 + 8 <= d.img_w;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int e = x0 + c;  // image row
+            if (e >= d.img_h) continue;
+            T* p = reinterpret_cast<T*>(d.dst) + (long long)e * d.dst_ld + R0;
+            T v[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[r] = a[r][c];
+            if (all_cols) {
+                acc_store8<T>(p, v, d.accumulate != 0);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (R0 + r < d.img_w) p[r] = d.accumulate ? (T)(p[r] + v[r]) : v[r];
             }
         }
     }
 }
 
-template <typename T, int GB>
-__global__ __launch_bounds__(kThreads) void fht_adj_pass_kernel(const AdjLaunch L)
+template <typename T, int GB, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kThreads, 4) void fht_adj_pass_kernel(const AdjLaunch L)
 {
-    __shared__ T lds[kTileRows * kLdsRow];
+    __shared__ T lds[kTileRows / 2 * kLdsRow];
     const AdjDesc& d = L.d[blockIdx.z];
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
-    if (d.dir > 0) adj_tile<T, GB, 1>(d, blockIdx.y, blockIdx.x, lds);
-    else adj_tile<T, GB, -1>(d, blockIdx.y, blockIdx.x, lds);
+    if (d.dir > 0) adj_tile<T, GB, 1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
+    else adj_tile<T, GB, -1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
 }
 
 // Adjoint for n <= 4 rows: B_j from B_{j+1} by the transposed stage, top-down.
@@ -528,8 +927,9 @@ __device__ T adj_direct(const AdjDesc& d, int row, int x)
 {
     if constexpr (J == K) {
         T v[8];
-        adj_load_row<T>(d, row, x, v);  // only v[0] is used
-        return v[0];
+        int e0;
+        if (adj_issue_row<T, true>(d, row, x, 0, v, e0)) adj_patch_row<T, true>(d, row, e0, v);
+        return v[0];  // only the first column is used
     } else {
         const int blk = 1 << J;
         const int base = (row / (2 * blk)) * (2 * blk);

@@ -75,9 +75,9 @@ struct AdjLaunch {
     int nd;
 };
 
-hipError_t launch_pass(const PassLaunch& L, int G, int in_t, int acc_t, hipStream_t s);
+hipError_t launch_pass(const PassLaunch& L, int G, bool first, bool last, int in_t, int acc_t, hipStream_t s);
 hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s);
-hipError_t launch_adjoint_pass(const AdjLaunch& L, int G, int t, hipStream_t s);
+hipError_t launch_adjoint_pass(const AdjLaunch& L, int G, bool first, bool last, int t, hipStream_t s);
 hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s);
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,

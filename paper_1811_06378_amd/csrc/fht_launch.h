@@ -17,18 +17,29 @@ inline dim3 pass_grid(const PassLaunch& L)
     return dim3(wx, ry, L.nd);
 }
 
-template <typename TIn, typename T>
-hipError_t launch_pass_t(const PassLaunch& L, int G, hipStream_t s)
+template <typename TIn, typename T, bool FIRST, bool LAST>
+hipError_t launch_pass_fl(const PassLaunch& L, int G, hipStream_t s)
 {
     const dim3 grid = pass_grid(L);
     switch (G) {
-    case 3: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 0>), grid, dim3(kThreads), 0, s, L); break;
-    case 4: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 1>), grid, dim3(kThreads), 0, s, L); break;
-    case 5: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 2>), grid, dim3(kThreads), 0, s, L); break;
-    case 6: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 3>), grid, dim3(kThreads), 0, s, L); break;
+    case 3: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 0, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
+    case 4: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 1, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
+    case 5: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 2, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
+    case 6: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 3, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// first = the pass reads the image, last = the pass writes the Hough image
+template <typename TIn, typename T>
+hipError_t launch_pass_t(const PassLaunch& L, int G, bool first, bool last, hipStream_t s)
+{
+    if (first) return last ? launch_pass_fl<TIn, T, true, true>(L, G, s) : launch_pass_fl<TIn, T, true, false>(L, G, s);
+    if constexpr (sizeof(TIn) == sizeof(T)) {
+        return last ? launch_pass_fl<T, T, false, true>(L, G, s) : launch_pass_fl<T, T, false, false>(L, G, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename TIn, typename T>
@@ -49,8 +60,8 @@ hipError_t launch_direct_t(const PassLaunch& L, int k, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_adj_pass_t(const AdjLaunch& L, int G, hipStream_t s)
+template <typename T, bool FIRST, bool LAST>
+hipError_t launch_adj_pass_fl(const AdjLaunch& L, int G, hipStream_t s)
 {
     int wx = 1, ry = 1;
     for (int i = 0; i < L.nd; ++i) {
@@ -59,13 +70,21 @@ hipError_t launch_adj_pass_t(const AdjLaunch& L, int G, hipStream_t s)
     }
     const dim3 grid(wx, ry, L.nd);
     switch (G) {
-    case 3: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 0>), grid, dim3(kThreads), 0, s, L); break;
-    case 4: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 1>), grid, dim3(kThreads), 0, s, L); break;
-    case 5: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 2>), grid, dim3(kThreads), 0, s, L); break;
-    case 6: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 3>), grid, dim3(kThreads), 0, s, L); break;
+    case 3: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 0, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
+    case 4: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 1, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
+    case 5: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 2, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
+    case 6: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 3, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// first = reads the Hough gradient, last = writes the image gradient
+template <typename T>
+hipError_t launch_adj_pass_t(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s)
+{
+    if (first) return last ? launch_adj_pass_fl<T, true, true>(L, G, s) : launch_adj_pass_fl<T, true, false>(L, G, s);
+    return last ? launch_adj_pass_fl<T, false, true>(L, G, s) : launch_adj_pass_fl<T, false, false>(L, G, s);
 }
 
 template <typename T>
@@ -88,14 +107,14 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
 }
 
 // per-type entry points (defined in the instantiation units)
-hipError_t launch_pass_u8(const PassLaunch& L, int G, hipStream_t s);
-hipError_t launch_pass_i32(const PassLaunch& L, int G, hipStream_t s);
-hipError_t launch_pass_f32(const PassLaunch& L, int G, hipStream_t s);
+hipError_t launch_pass_u8(const PassLaunch& L, int G, bool first, bool last, hipStream_t s);
+hipError_t launch_pass_i32(const PassLaunch& L, int G, bool first, bool last, hipStream_t s);
+hipError_t launch_pass_f32(const PassLaunch& L, int G, bool first, bool last, hipStream_t s);
 hipError_t launch_direct_u8(const PassLaunch& L, int k, hipStream_t s);
 hipError_t launch_direct_i32(const PassLaunch& L, int k, hipStream_t s);
 hipError_t launch_direct_f32(const PassLaunch& L, int k, hipStream_t s);
-hipError_t launch_adj_pass_i32(const AdjLaunch& L, int G, hipStream_t s);
-hipError_t launch_adj_pass_f32(const AdjLaunch& L, int G, hipStream_t s);
+hipError_t launch_adj_pass_i32(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s);
+hipError_t launch_adj_pass_f32(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s);
 hipError_t launch_adj_direct_i32(const AdjLaunch& L, int k, hipStream_t s);
 hipError_t launch_adj_direct_f32(const AdjLaunch& L, int k, hipStream_t s);
 

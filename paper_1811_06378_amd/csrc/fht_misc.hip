@@ -15,11 +15,11 @@ __global__ void fht_zero_kernel(uint32_t* p, int64_t rows, int64_t cols_words, i
 }
 
 // dtype codes: 0 = u8, 1 = i32, 2 = f32
-hipError_t launch_pass(const PassLaunch& L, int G, int in_t, int acc_t, hipStream_t s)
+hipError_t launch_pass(const PassLaunch& L, int G, bool first, bool last, int in_t, int acc_t, hipStream_t s)
 {
-    if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, G, s);
-    if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, G, s);
-    if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, G, s);
+    if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, G, first, last, s);
+    if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, G, first, last, s);
+    if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, G, first, last, s);
     return hipErrorInvalidValue;
 }
 
@@ -31,10 +31,10 @@ hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStr
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_adjoint_pass(const AdjLaunch& L, int G, int t, hipStream_t s)
+hipError_t launch_adjoint_pass(const AdjLaunch& L, int G, bool first, bool last, int t, hipStream_t s)
 {
-    if (t == 1) return launch_adj_pass_i32(L, G, s);
-    if (t == 2) return launch_adj_pass_f32(L, G, s);
+    if (t == 1) return launch_adj_pass_i32(L, G, first, last, s);
+    if (t == 2) return launch_adj_pass_f32(L, G, first, last, s);
     return hipErrorInvalidValue;
 }
 
