@@ -1,10 +1,7 @@
-// Adjoint pass kernels for the int accumulator.
+// Adjoint kernels for the int accumulator.
 #include "fht_launch.h"
 
 namespace fht {
-hipError_t launch_adj_pass_i32(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s)
-{
-    return launch_adj_pass_t<int>(L, G, first, last, s);
-}
+hipError_t launch_adj_pass_i32(const AdjLaunch& L, hipStream_t s) { return launch_adj_pass_t<int>(L, s); }
 hipError_t launch_adj_direct_i32(const AdjLaunch& L, int k, hipStream_t s) { return launch_adj_direct_t<int>(L, k, s); }
 }  // namespace fht

@@ -1,6 +1,6 @@
 // C ABI of libfht.so (declared in include/fht.h): argument validation, pass
 // planning, workspace layout and launch orchestration.  All arithmetic runs in
-// the kernels of fht_kernels.hip and fht_batch.hip.
+// the kernels of fht_device.h.
 
 #include "fht.h"
 #include "fht_internal.h"
@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 namespace fht {
 
@@ -44,6 +45,8 @@ int ilog2(int64_t p)
     return k;
 }
 
+// Stage-fusion split: k stages in ceil(k/6) passes of 3..6 stages, larger
+// passes first (k <= 2 runs as one direct pass).
 void pass_split(int k, int* npass, int* G)
 {
     if (k <= 2) {
@@ -57,29 +60,37 @@ void pass_split(int k, int* npass, int* G)
     *npass = np;
 }
 
-// Geometry of quadrant q (1..4) of an h x w image; S1 != 0 adds the range shear.
+// Geometry of quadrant q (1..4) of an h x w image; S1 != 0 adds the range shear
+// (unmirrored quadrants only).
 QuadGeom quad_geom(int w, int h, int q, int S1)
 {
     QuadGeom g{};
     const int hp = (int)pow2_ceil(h), wp = (int)pow2_ceil(w);
     g.q = q;
     g.transposed = q >= 3;
+    g.mirror = (q == 2 || q == 3) ? 1 : 0;
     g.n = g.transposed ? wp : hp;
     g.other = g.transposed ? hp : wp;
     g.W = hp + wp;
     g.k = ilog2(g.n);
-    g.dir = (q == 1 || q == 4) ? 1 : -1;
     pass_split(g.k, &g.npass, g.G);
     int j = 0;
     for (int p = 0; p < g.npass; ++p) {
         j += g.G[p];
         g.j_end[p] = j;
-        // nonzero logical columns after j stages: the image's columns moved by
-        // the shear (rows roll right by 0..S1) widened by 2^j - 1 on the side the
-        // patterns lean to
+        // nonzero columns after j stages, in xi: unmirrored, the image columns
+        // moved by the shear (rows roll right by 0..S1) and widened by 2^j - 1
+        // towards negative xi; mirrored, x in [0, other + 2^j - 1) i.e.
+        // xi in [-(other + 2^j - 2), 0]
         const int64_t spread = (int64_t(1) << j) - 1;
-        int64_t lo = (S1 < 0 ? S1 : 0) - (g.dir > 0 ? spread : 0);
-        int64_t hi = (S1 > 0 ? S1 : 0) + g.other + (g.dir < 0 ? spread : 0);
+        int64_t lo, hi;
+        if (!g.mirror) {
+            lo = (S1 < 0 ? S1 : 0) - spread;
+            hi = (S1 > 0 ? S1 : 0) + g.other;
+        } else {
+            lo = -(g.other + spread - 1);
+            hi = 1;
+        }
         // band origin on a 64-column boundary keeps the tile windows aligned
         lo = -(((-lo) + 63) / 64) * 64;
         int64_t bw = hi - lo;
@@ -96,10 +107,11 @@ size_t quad_band_bytes(const QuadGeom& g, int p, int elem)
     return ((size_t)g.n * (size_t)g.band_ld[p] * (size_t)elem + 255) / 256 * 256;
 }
 
-// Lays out the intermediate bands of the selected quadrants; returns total bytes.
-size_t layout_bands(QuadGeom* gs, int nq, int elem)
+// Lays out the intermediate bands of the selected quadrants after `base`
+// bytes; returns the end offset.
+size_t layout_bands(QuadGeom* gs, int nq, int elem, size_t base)
 {
-    size_t off = 0;
+    size_t off = base;
     for (int i = 0; i < nq; ++i)
         for (int p = 0; p + 1 < gs[i].npass; ++p) {
             gs[i].band_byte_off[p] = off;
@@ -133,8 +145,7 @@ int selected_quads(unsigned quads, int* qs)
 }
 
 // Hough row placement of quadrant q's shift s.
-void placement(int w, int h, unsigned quads, int q, int* base, int* sign, int* skip, int* roll_a,
-               int* roll_b)
+void placement(int w, int h, unsigned quads, int q, int* base, int* sign, int* skip, int* roll_a, int* roll_b)
 {
     const int hp = (int)pow2_ceil(h), wp = (int)pow2_ceil(w);
     *roll_a = (q <= 2) ? hp : wp;
@@ -157,13 +168,326 @@ void placement(int w, int h, unsigned quads, int q, int* base, int* sign, int* s
     *skip = -1;
 }
 
+// FHT_NT=0 writes the Hough image with ordinary stores instead of streaming
+// (non-temporal) ones.
+static int stream_stores()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("FHT_NT");
+        v = (e && e[0] == '0') ? 0 : 1;
+    }
+    return v;
+}
+
+// Descriptor of forward pass p of quadrant geometry g.
+PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int w, int h, int64_t ld_img, void* hough,
+                        int64_t ld_hough, unsigned char* ws, int S1, int row_limit_final, int base, int sign,
+                        int skip, int shifted, int roll_a, int roll_b)
+{
+    PassDesc d{};
+    const int G = g.G[p];
+    const int VW = kWinCols - (1 << G);
+    d.n = g.n;
+    d.W = g.W;
+    d.j0 = p == 0 ? 0 : g.j_end[p - 1];
+    d.G = G;
+    d.mirror = g.mirror;
+    d.img_w = w;
+    d.img_h = h;
+    d.n_row_tiles = (g.n + kTileRows - 1) / kTileRows;
+    if (p == 0) {
+        d.src = img;
+        d.src_ld = ld_img;
+        d.src_kind = g.transposed ? SRC_IMAGE_T : SRC_IMAGE;
+        d.S1 = S1;
+    } else {
+        d.src = ws + g.band_byte_off[p - 1];
+        d.src_ld = g.band_ld[p - 1];
+        d.src_kind = SRC_BAND;
+        d.src_off = g.band_off[p - 1];
+        d.src_bw = g.band_w[p - 1];
+    }
+    if (p == g.npass - 1) {
+        d.dst = hough;
+        d.dst_ld = ld_hough;
+        d.dst_kind = DST_HOUGH;
+        d.x_start = 0;
+        d.n_windows = (g.W + VW - 1) / VW;
+        d.row_limit = row_limit_final;
+        d.row_base = base;
+        d.row_sign = sign;
+        d.skip_row = skip;
+        d.shifted = shifted;
+        d.roll_a = roll_a;
+        d.roll_b = roll_b;
+        // black zone of row s (section 3.2): xi in [other, other + n - s)
+        // unmirrored, [1, 1 + n - s) mirrored; not with a shear
+        d.black_lo = g.mirror ? 1 : g.other;
+        d.black_ok = (S1 == 0) ? 1 : 0;
+        d.stream_store = stream_stores();
+    } else {
+        d.dst = ws + g.band_byte_off[p];
+        d.dst_ld = g.band_ld[p];
+        d.dst_kind = DST_BAND;
+        d.dst_off = g.band_off[p];
+        d.dst_bw = g.band_w[p];
+        d.x_start = -g.band_off[p];
+        d.n_windows = (g.band_w[p] + VW - 1) / VW;
+        d.row_limit = row_limit_final == INT_MAX ? INT_MAX : (row_limit_final >> (g.k - g.j_end[p]));
+        d.skip_row = -1;
+    }
+    return d;
+}
+
+int append_engine_groups(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, std::vector<EngineGroup>& out,
+                         int first_item)
+{
+    int maxp = 0;
+    for (int i = 0; i < nq; ++i)
+        if (gs[i].k > 2 && gs[i].npass > maxp) maxp = gs[i].npass;
+    int group_of[4][4];
+    int item = first_item;
+    for (int step = 0; step < nq + maxp; ++step) {
+        for (int p = 0; p < maxp; ++p) {
+            const int i = step - p;
+            if (i < 0 || i >= nq || gs[i].k <= 2 || p >= gs[i].npass) continue;
+            EngineGroup e{};
+            e.d = descs[i][p];
+            e.first_item = item;
+            e.count = e.d.n_row_tiles * e.d.n_windows;
+            e.dep = p > 0 ? group_of[i][p - 1] : -1;
+            e.dep_count = p > 0 ? out[group_of[i][p - 1]].count : 0;
+            e.notify = p + 1 < gs[i].npass ? 1 : 0;
+            group_of[i][p] = (int)out.size();
+            out.push_back(e);
+            item += e.count;
+        }
+    }
+    return item - first_item;
+}
+
+// Iterations of the bounded dependency wait (each sleeps ~256 cycles plus
+// the atomic's round trip): far beyond any legitimate wait, short enough that
+// a planner error surfaces as FHT_ERR_TIMEOUT within seconds.
+int engine_spin_limit()
+{
+    static int lim = -1;
+    if (lim < 0) {
+        const char* e = getenv("FHT_SPIN_LIMIT");
+        lim = e ? atoi(e) : (1 << 21);
+        if (lim < 1) lim = 1;
+    }
+    return lim;
+}
+
+// Launches the engine over `groups` (queue order, dependencies pointing
+// backwards).  Groups of different depth G run in separate launches, deepest
+// first: a quadrant's passes have non-increasing depth, so a dependency on a
+// group of another depth is on an earlier launch and stream order covers it.
+// FHT_ACQUIRE=0 selects the light acquire after a dependency wait (see
+// wait_group); the default is the agent-scope acquire.
+int engine_agent_acquire()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("FHT_ACQUIRE");
+        v = (e && e[0] == '0') ? 0 : 1;
+    }
+    return v;
+}
+
+int run_engine(const std::vector<EngineGroup>& groups, const EngineGroup* dev_table, int total_items,
+               unsigned* sync, int in_t, int acc_t, hipStream_t stream)
+{
+    (void)total_items;
+    (void)dev_table;
+    if (groups.empty()) return FHT_OK;
+    const int grid_max = engine_grid_size();
+    for (int G = kMaxG; G >= 3; --G) {
+        std::vector<int> remap(groups.size(), -1);
+        EngineArgs A{};
+        int item = 0;
+        int n = 0;
+        for (size_t i = 0; i < groups.size(); ++i) {
+            if (groups[i].d.G != G) continue;
+            if (n >= kEngineInline) return fail(FHT_ERR_UNSUPPORTED, "too many engine groups of one depth");
+            EngineGroup e = groups[i];
+            e.first_item = item;
+            e.dep = (e.dep >= 0 && remap[e.dep] >= 0) ? remap[e.dep] : -1;
+            remap[i] = n;
+            A.g[n++] = e;
+            item += e.count;
+        }
+        if (n == 0) continue;
+        A.n_groups = n;
+        A.total_items = item;
+        A.sync = sync;
+        A.spin_limit = engine_spin_limit();
+        A.agent_acquire = engine_agent_acquire();
+        A.table = nullptr;
+        hipError_t e = launch_zero(sync, 1, n + 2, n + 2, 4, stream);
+        if (e != hipSuccess) return hip_fail(e, "engine counter reset");
+        e = launch_engine(A, G, item < grid_max ? item : grid_max, in_t, acc_t, stream);
+        if (e != hipSuccess) return hip_fail(e, "engine launch");
+    }
+    return FHT_OK;
+}
+
+// FHT_ORDER: 0 = every quadrant's pass p in one launch, 2 = quadrant pairs.
+static int launch_order()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("FHT_ORDER");
+        v = e ? atoi(e) : 0;
+    }
+    return v;
+}
+
+// FHT_ENGINE=1 selects the persistent engine instead of one launch per pass.
+static bool use_engine()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("FHT_ENGINE");
+        v = (e && e[0] == '1') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+// Side streams and events of the quadrant pipeline, one set per device.
+struct Pipeline {
+    bool ready = false;
+    hipStream_t s[4];
+    hipEvent_t start, p0_done[4], done[4];
+};
+static std::mutex g_pipe_mu;
+static Pipeline g_pipes[64];
+
+static int pipeline_for_current_device(Pipeline** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(FHT_ERR_UNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lock(g_pipe_mu);
+    Pipeline& P = g_pipes[dev];
+    if (!P.ready) {
+        // default-priority, non-blocking side streams; events without timing
+        for (int i = 0; i < 4; ++i) {
+            if ((e = hipStreamCreateWithFlags(&P.s[i], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+            if ((e = hipEventCreateWithFlags(&P.p0_done[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+            if ((e = hipEventCreateWithFlags(&P.done[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+        }
+        if ((e = hipEventCreateWithFlags(&P.start, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+        P.ready = true;
+    }
+    *out = &P;
+    return FHT_OK;
+}
+
+static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t, unsigned* sync,
+                       hipStream_t stream);
+
+// Quadrant pipeline: quadrant i runs on its own stream and starts its first
+// pass when quadrant i-1's first pass is done, so at most two quadrants'
+// bands are live (they stay in the last-level cache between write and read)
+// while the passes of neighbouring quadrants overlap.  Forks from and joins
+// back to the caller's stream.
+static int run_forward_pipelined(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t,
+                                 unsigned* sync, hipStream_t stream)
+{
+    Pipeline* P = nullptr;
+    int rc = pipeline_for_current_device(&P);
+    if (rc) return rc;
+    hipError_t e = hipEventRecord(P->start, stream);
+    if (e != hipSuccess) return hip_fail(e, "event record");
+    for (int i = 0; i < nq; ++i) {
+        hipStream_t si = P->s[i];
+        if ((e = hipStreamWaitEvent(si, P->start, 0)) != hipSuccess) return hip_fail(e, "stream wait");
+        if (i > 0 && (e = hipStreamWaitEvent(si, P->p0_done[i - 1], 0)) != hipSuccess) return hip_fail(e, "stream wait");
+        for (int p = 0; p < gs[i].npass; ++p) {
+            PassLaunch L{};
+            L.d[0] = descs[i][p];
+            L.nd = 1;
+            if (gs[i].k <= 2) e = launch_direct(L, gs[i].k, in_t, acc_t, si);
+            else e = launch_pass(L, p == 0 ? in_t : acc_t, acc_t, si);
+            if (e != hipSuccess) return hip_fail(e, "pipelined pass launch");
+            if (p == 0 && (e = hipEventRecord(P->p0_done[i], si)) != hipSuccess) return hip_fail(e, "event record");
+        }
+        if ((e = hipEventRecord(P->done[i], si)) != hipSuccess) return hip_fail(e, "event record");
+    }
+    for (int i = 0; i < nq; ++i)
+        if ((e = hipStreamWaitEvent(stream, P->done[i], 0)) != hipSuccess) return hip_fail(e, "stream wait");
+    (void)sync;
+    return FHT_OK;
+}
+
+// Runs the forward passes of the quadrant geometries gs[0..nq).
+static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t, unsigned* sync,
+                       hipStream_t stream)
+{
+    if (launch_order() == 3 && nq > 1 && !use_engine()) return run_forward_pipelined(gs, descs, nq, in_t, acc_t, sync, stream);
+    // quadrant pairs (1, 2) and (3, 4) one after the other: a pair's bands
+    // plus the image stay within the last-level cache between the passes
+    if (launch_order() == 2 && nq > 2) {
+        for (int i = 0; i < nq; i += 2) {
+            const int m = (nq - i) < 2 ? (nq - i) : 2;
+            int rc = run_forward(gs + i, descs + i, m, in_t, acc_t, sync, stream);
+            if (rc) return rc;
+        }
+        return FHT_OK;
+    }
+    // quadrants with at most two stages: one direct launch
+    for (int i = 0; i < nq; ++i) {
+        if (gs[i].k > 2) continue;
+        PassLaunch L{};
+        L.d[0] = descs[i][0];
+        L.nd = 1;
+        hipError_t e = launch_direct(L, gs[i].k, in_t, acc_t, stream);
+        if (e != hipSuccess) return hip_fail(e, "direct launch");
+    }
+    if (use_engine()) {
+        std::vector<EngineGroup> groups;
+        const int total = append_engine_groups(gs, descs, nq, groups, 0);
+        return run_engine(groups, nullptr, total, sync, in_t, acc_t, stream);
+    }
+    int maxp = 0;
+    for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
+    for (int p = 0; p < maxp; ++p) {
+        for (int G = kMaxG; G >= 3; --G) {
+            for (int last = 0; last < 2; ++last) {
+                PassLaunch L{};
+                for (int i = 0; i < nq; ++i)
+                    if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (last == 1))
+                        L.d[L.nd++] = descs[i][p];
+                if (L.nd == 0) continue;
+                const int ti = p == 0 ? in_t : acc_t;
+                hipError_t e = launch_pass(L, ti, acc_t, stream);
+                if (e != hipSuccess) return hip_fail(e, "forward pass launch");
+            }
+        }
+    }
+    return FHT_OK;
+}
+
+// Workspace: engine counters, then the intermediate bands.
+static size_t forward_workspace(QuadGeom* gs, int nq, int acc_t)
+{
+    int groups = 0;
+    for (int i = 0; i < nq; ++i)
+        if (gs[i].k > 2) groups += gs[i].npass;
+    return layout_bands(gs, nq, elem_size(acc_t), engine_sync_bytes(groups));
+}
+
 }  // namespace fht
 
 using namespace fht;
 
 extern "C" {
 
-int fht_version(void) { return 10000; }
+int fht_version(void) { return 10100; }
 
 const char* fht_status_string(int status)
 {
@@ -234,14 +558,23 @@ int fht_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, size_t
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    *bytes = layout_bands(gs, nq, elem_size(acc_t));
+    *bytes = forward_workspace(gs, nq, acc_t);
     return FHT_OK;
 }
 
 int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* bytes)
 {
+    if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
     if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "adjoint type must be I32 or F32");
-    return fht_workspace_size(w, h, quads, t, t, bytes);
+    int64_t r, c;
+    int rc = fht_hough_shape(w, h, quads, &r, &c);
+    if (rc) return rc;
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    *bytes = layout_bands(gs, nq, 4, 0);
+    return FHT_OK;
 }
 
 int fht_range_workspace_size(int w, int h, int S1, int S, int transposed, int in_t, int acc_t, size_t* bytes)
@@ -252,122 +585,12 @@ int fht_range_workspace_size(int w, int h, int S1, int S, int transposed, int in
     if (rc) return rc;
     if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
     QuadGeom g = quad_geom(w, h, transposed ? 4 : 1, S1);
-    *bytes = layout_bands(&g, 1, elem_size(acc_t));
+    *bytes = forward_workspace(&g, 1, acc_t);
     return FHT_OK;
 }
 
-}  // extern "C"
-
-namespace fht {
-
-// Fills the descriptor of forward pass p of quadrant geometry g.
-PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int in_src_kind, int w, int h,
-                        int64_t ld_img, void* hough, int64_t ld_hough, unsigned char* ws, int S1,
-                        int row_limit_final, int base, int sign, int skip, int shifted, int roll_a,
-                        int roll_b)
-{
-    PassDesc d{};
-    const int G = g.G[p];
-    const int VW = kWinCols - (1 << G);
-    d.n = g.n;
-    d.W = g.W;
-    d.j0 = p == 0 ? 0 : g.j_end[p - 1];
-    d.dir = g.dir;
-    d.img_w = w;
-    d.img_h = h;
-    d.n_row_tiles = (g.n + kTileRows - 1) / kTileRows;
-    if (p == 0) {
-        d.src = img;
-        d.src_ld = ld_img;
-        d.src_kind = in_src_kind;
-        d.S1 = S1;
-    } else {
-        d.src = ws + g.band_byte_off[p - 1];
-        d.src_ld = g.band_ld[p - 1];
-        d.src_kind = SRC_BAND;
-        d.src_off = g.band_off[p - 1];
-        d.src_bw = g.band_w[p - 1];
-    }
-    const bool last = p == g.npass - 1;
-    if (last) {
-        d.dst = hough;
-        d.dst_ld = ld_hough;
-        d.dst_kind = DST_HOUGH;
-        d.x_start = 0;
-        d.n_windows = (g.W + VW - 1) / VW;
-        d.row_limit = row_limit_final;
-        d.row_base = base;
-        d.row_sign = sign;
-        d.skip_row = skip;
-        d.shifted = shifted;
-        d.roll_a = roll_a;
-        d.roll_b = roll_b;
-    } else {
-        d.dst = ws + g.band_byte_off[p];
-        d.dst_ld = g.band_ld[p];
-        d.dst_kind = DST_BAND;
-        d.dst_off = g.band_off[p];
-        d.dst_bw = g.band_w[p];
-        d.x_start = -g.band_off[p];
-        d.n_windows = (g.band_w[p] + VW - 1) / VW;
-        d.row_limit = row_limit_final == INT_MAX ? INT_MAX : (row_limit_final >> (g.k - g.j_end[p]));
-        d.skip_row = -1;
-    }
-    return d;
-}
-
-// Runs the forward passes of the quadrant geometries gs[0..nq) (all already
-// described by descs[i][p]); one launch per (pass index, fusion depth).
-// Launch order: 0 = pass-major (one launch per pass covers every quadrant),
-// 1 = quadrant-major (a quadrant's passes run back to back, so its band is
-// read again while it is still cached).  FHT_ORDER overrides the default.
-static int launch_order()
-{
-    static int order = -1;
-    if (order < 0) {
-        const char* e = getenv("FHT_ORDER");
-        order = (e && e[0] == '1') ? 1 : 0;
-    }
-    return order;
-}
-
-int run_forward_passes(const QuadGeom* gs, PassDesc (*descs)[4], int nq, int in_t, int acc_t,
-                       hipStream_t stream)
-{
-    if (launch_order() == 1 && nq > 1) {
-        for (int i = 0; i < nq; ++i) {
-            int rc = run_forward_passes(&gs[i], &descs[i], 1, in_t, acc_t, stream);
-            if (rc) return rc;
-        }
-        return FHT_OK;
-    }
-    int maxp = 0;
-    for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
-    for (int p = 0; p < maxp; ++p) {
-        for (int G = 0; G <= kMaxG; ++G) {
-            for (int last = 0; last < 2; ++last) {
-                PassLaunch L{};
-                for (int i = 0; i < nq; ++i)
-                    if (p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (last != 0))
-                        L.d[L.nd++] = descs[i][p];
-                if (L.nd == 0) continue;
-                const int ti = p == 0 ? in_t : acc_t;
-                hipError_t e = G <= 2 ? launch_direct(L, G, ti, acc_t, stream)
-                                      : launch_pass(L, G, p == 0, last != 0, ti, acc_t, stream);
-                if (e != hipSuccess) return hip_fail(e, "forward pass launch");
-            }
-        }
-    }
-    return FHT_OK;
-}
-
-}  // namespace fht
-
-extern "C" {
-
-int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t,
-                int64_t ld_hough, unsigned quads, unsigned flags, void* workspace, size_t ws_bytes,
-                void* stream)
+int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t, int64_t ld_hough,
+                unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream)
 {
     int64_t rows, cols;
     int rc = fht_hough_shape(w, h, quads, &rows, &cols);
@@ -383,25 +606,23 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    const size_t need = layout_bands(gs, nq, elem_size(acc_t));
-    if (need > 0 && (!workspace || ws_bytes < need))
+    const size_t need = forward_workspace(gs, nq, acc_t);
+    if (!workspace || ws_bytes < need)
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
-    if (workspace && ((uintptr_t)workspace & 255))
-        return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
     PassDesc descs[4][4];
     for (int i = 0; i < nq; ++i) {
         int base, sign, skip, ra, rb;
         placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
         for (int p = 0; p < gs[i].npass; ++p)
-            descs[i][p] = make_pass_desc(gs[i], p, img, gs[i].transposed ? SRC_IMAGE_T : SRC_IMAGE, w, h,
-                                         ld_img, hough, ld_hough, (unsigned char*)workspace, 0, INT_MAX,
-                                         base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb);
+            descs[i][p] = make_pass_desc(gs[i], p, img, w, h, ld_img, hough, ld_hough, (unsigned char*)workspace, 0,
+                                         INT_MAX, base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb);
     }
-    return run_forward_passes(gs, descs, nq, in_t, acc_t, (hipStream_t)stream);
+    return run_forward(gs, descs, nq, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream);
 }
 
-int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, int S, int transposed,
-              void* hough, int acc_t, int64_t ld_hough, void* workspace, size_t ws_bytes, void* stream)
+int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, int S, int transposed, void* hough,
+              int acc_t, int64_t ld_hough, void* workspace, size_t ws_bytes, void* stream)
 {
     int64_t rows, cols;
     int rc = fht_range_shape(w, h, S1, S, transposed, &rows, &cols);
@@ -411,20 +632,18 @@ int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, i
     if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
     if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
     QuadGeom g = quad_geom(w, h, transposed ? 4 : 1, S1);
-    const size_t need = layout_bands(&g, 1, elem_size(acc_t));
-    if (need > 0 && (!workspace || ws_bytes < need))
+    const size_t need = forward_workspace(&g, 1, acc_t);
+    if (!workspace || ws_bytes < need)
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
-    if (workspace && ((uintptr_t)workspace & 255))
-        return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
     PassDesc descs[1][4];
     for (int p = 0; p < g.npass; ++p)
-        descs[0][p] = make_pass_desc(g, p, img, transposed ? SRC_IMAGE_T : SRC_IMAGE, w, h, ld_img, hough,
-                                     ld_hough, (unsigned char*)workspace, S1, S, 0, 1, -1, 0, 0, 0);
-    return run_forward_passes(&g, descs, 1, in_t, acc_t, (hipStream_t)stream);
+        descs[0][p] = make_pass_desc(g, p, img, w, h, ld_img, hough, ld_hough, (unsigned char*)workspace, S1, S, 0, 1,
+                                     -1, 0, 0, 0);
+    return run_forward(&g, descs, 1, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream);
 }
 
-int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, int w, int h, int inverse,
-              void* stream)
+int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, int w, int h, int inverse, void* stream)
 {
     int rc = check_sides(w, h);
     if (rc) return rc;
@@ -448,9 +667,9 @@ int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, i
 
 namespace fht {
 
-AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_grad, void* gimg, int64_t ld_img,
-                      int w, int h, unsigned char* ws, int base, int sign, int skip, int shifted, int roll_a,
-                      int roll_b, int accumulate)
+AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_grad, void* gimg, int64_t ld_img, int w,
+                      int h, unsigned char* ws, int base, int sign, int skip, int shifted, int roll_a, int roll_b,
+                      int accumulate)
 {
     AdjDesc d{};
     const int G = g.G[p];
@@ -458,7 +677,8 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
     d.n = g.n;
     d.W = g.W;
     d.j0 = p == 0 ? 0 : g.j_end[p - 1];
-    d.dir = g.dir;
+    d.G = G;
+    d.mirror = g.mirror;
     d.img_w = w;
     d.img_h = h;
     d.n_row_tiles = (g.n + kTileRows - 1) / kTileRows;
@@ -485,8 +705,9 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
         d.dst_ld = ld_img;
         d.dst_kind = g.transposed ? 2 : 1;
         d.accumulate = accumulate;
+        // image columns 0..cols-1 are xi = x (unmirrored) or xi = W - x (mirrored)
         const int cols = g.transposed ? h : w;
-        d.x_start = 0;
+        d.x_start = g.mirror ? g.W - cols + 1 : 0;
         d.n_windows = (cols + VW - 1) / VW;
     } else {
         d.dst = ws + g.band_byte_off[p - 1];
@@ -521,11 +742,10 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    const size_t need = layout_bands(gs, nq, 4);
+    const size_t need = layout_bands(gs, nq, 4, 0);
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
-    if (workspace && ((uintptr_t)workspace & 255))
-        return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (workspace && ((uintptr_t)workspace & 255)) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
     AdjDesc descs[4][4];
     for (int i = 0; i < nq; ++i) {
         int base, sign, skip, ra, rb;
@@ -547,10 +767,10 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 for (int first = 0; first < 2; ++first) {
                     AdjLaunch L{};
                     for (int i = 0; i < nq; ++i)
-                        if (p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first != 0))
+                        if (p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first == 1))
                             L.d[L.nd++] = descs[i][p];
                     if (L.nd == 0) continue;
-                    hipError_t e = launch_adjoint_pass(L, G, first != 0, false, t, s);
+                    hipError_t e = launch_adjoint_pass(L, t, s);
                     if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
                 }
             }
@@ -559,9 +779,7 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 AdjLaunch L{};
                 L.d[0] = descs[i][0];
                 L.nd = 1;
-                const int G = gs[i].G[0];
-                hipError_t e = G <= 2 ? launch_adjoint_direct(L, G, t, s)
-                                      : launch_adjoint_pass(L, G, gs[i].npass == 1, true, t, s);
+                hipError_t e = gs[i].k <= 2 ? launch_adjoint_direct(L, gs[i].k, t, s) : launch_adjoint_pass(L, t, s);
                 if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
             }
         }

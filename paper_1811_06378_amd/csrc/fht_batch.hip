@@ -1,16 +1,258 @@
-// Batched forward: placeholder until the persistent kernel lands.
+// Batched forward over many images of different sizes (fht_batch_* in fht.h).
+//
+// A plan lays out, once, every pass of every quadrant of every image as an
+// engine group whose pointers are byte offsets: image index, offset in the
+// packed Hough buffer, offset in the workspace.  A call copies the template
+// into the workspace with the pointers resolved (one small kernel), then runs
+// one table-driven launch per (pass, depth, last-pass) class: every tile of
+// every image of that class in one grid.  Images are processed in chunks
+// whose intermediate bands fit a fixed budget, so the workspace stays
+// bounded; chunks follow each other on the stream.  Everything enqueued is a
+// kernel, so a call can be captured in a hipGraph.
+
 #include "fht.h"
+#include "fht_internal.h"
 #include "fht_plan.h"
 
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <vector>
+
+namespace fht {
+
+constexpr size_t kBatchBandBudget = size_t(2) << 30;  // bytes of bands per chunk
+
+struct BatchLaunch {
+    int first_group;  // index into the table
+    int n_groups;
+    int n_items;
+    int G;
+    bool first, last;
+};
+
+struct BatchTemplate {
+    int img;          // image index (image sources)
+    int src_is_ws;    // src offset is into the workspace (band), else image
+    int dst_is_ws;    // dst offset is into the workspace (band), else the Hough buffer
+    int pad_;
+    int64_t src_off;  // bytes
+    int64_t dst_off;  // bytes
+};
+
+// Copies the template table into the workspace with pointers resolved.
+__global__ void fht_batch_fixup_kernel(const EngineGroup* __restrict__ tmpl, const BatchTemplate* __restrict__ rel,
+                                       int n_groups, const void* const* imgs, unsigned char* hough,
+                                       unsigned char* ws, EngineGroup* out)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    EngineGroup e = tmpl[g];
+    const BatchTemplate r = rel[g];
+    e.d.src = r.src_is_ws ? (const void*)(ws + r.src_off) : imgs[r.img];
+    e.d.dst = r.dst_is_ws ? (void*)(ws + r.dst_off) : (void*)(hough + r.dst_off);
+    out[g] = e;
+}
+
+}  // namespace fht
+
+struct fht_batch_plan {
+    int n = 0;
+    unsigned quads = 0;
+    int in_t = 0, acc_t = 0;
+    int device = 0;
+    std::vector<int32_t> ws, hs;
+    std::vector<int64_t> out_off;
+    int64_t out_elems = 0;
+    size_t table_bytes = 0;   // resolved table at the start of the workspace
+    size_t ws_bytes = 0;
+    int n_groups = 0;
+    std::vector<fht::BatchLaunch> launches;  // in stream order (chunks, passes, classes)
+    fht::EngineGroup* d_tmpl = nullptr;
+    fht::BatchTemplate* d_rel = nullptr;
+};
+
+using namespace fht;
+
 extern "C" {
-int fht_batch_plan_create(const int32_t*, const int32_t*, int, unsigned, int, int, fht_batch_plan**, size_t*,
-                          int64_t*, int64_t*)
+
+int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned quads, int in_t, int acc_t,
+                          fht_batch_plan** plan, size_t* ws_bytes, int64_t* out_elems, int64_t* out_offsets)
 {
-    return fht::fail(FHT_ERR_UNSUPPORTED, "batched forward not built yet");
+    if (!ws || !hs || !plan || !ws_bytes || !out_elems || n < 1) return fail(FHT_ERR_INVALID, "bad batch arguments");
+    *plan = nullptr;
+    if (!((in_t == FHT_U8 && acc_t == FHT_I32) || (in_t == FHT_I32 && acc_t == FHT_I32) ||
+          (in_t == FHT_F32 && acc_t == FHT_F32)))
+        return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    if (quads == 0 || (quads & ~15u)) return fail(FHT_ERR_INVALID, "bad quadrant selection 0x%x", quads);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_sides(ws[i], hs[i]);
+        if (rc) return rc;
+        if (ws[i] < 5 || hs[i] < 5)
+            return fail(FHT_ERR_UNSUPPORTED, "batched images need sides >= 5 (image %d is %dx%d)", i, hs[i], ws[i]);
+    }
+    fht_batch_plan* P = new fht_batch_plan();
+    P->n = n;
+    P->quads = quads;
+    P->in_t = in_t;
+    P->acc_t = acc_t;
+    P->ws.assign(ws, ws + n);
+    P->hs.assign(hs, hs + n);
+    hipGetDevice(&P->device);
+
+    // output layout: image after image, each dense (ld = W_i)
+    P->out_off.resize(n);
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t r, c;
+        fht_hough_shape(ws[i], hs[i], quads, &r, &c);
+        P->out_off[i] = off;
+        off += r * c;
+    }
+    P->out_elems = off;
+    const int esz = 4;
+
+    // per image geometry and descriptors (pointers as offsets)
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    std::vector<EngineGroup> tmpl;
+    std::vector<BatchTemplate> rel;
+    size_t band_peak = 0;
+    // chunks of images with bounded band memory
+    int i0 = 0;
+    while (i0 < n) {
+        size_t band = 0;
+        int i1 = i0;
+        std::vector<QuadGeom> geoms;
+        while (i1 < n) {
+            QuadGeom gs[4];
+            for (int q = 0; q < nq; ++q) gs[q] = quad_geom(ws[i1], hs[i1], qs[q], 0);
+            const size_t b = layout_bands(gs, nq, esz, 0);
+            if (i1 > i0 && band + b > kBatchBandBudget) break;
+            for (int q = 0; q < nq; ++q) {
+                for (int p = 0; p + 1 < gs[q].npass; ++p) gs[q].band_byte_off[p] += band;
+                geoms.push_back(gs[q]);
+            }
+            band += b;
+            ++i1;
+        }
+        band_peak = std::max(band_peak, band);
+        // groups of this chunk, by (pass, depth, last)
+        struct Item { EngineGroup e; BatchTemplate r; int p, G, last; };
+        std::vector<Item> items;
+        for (int i = i0; i < i1; ++i) {
+            for (int q = 0; q < nq; ++q) {
+                const QuadGeom& g = geoms[(size_t)(i - i0) * nq + q];
+                int base, sign, skip, ra, rb;
+                placement(ws[i], hs[i], quads, qs[q], &base, &sign, &skip, &ra, &rb);
+                int64_t r, c;
+                fht_hough_shape(ws[i], hs[i], quads, &r, &c);
+                for (int p = 0; p < g.npass; ++p) {
+                    Item it{};
+                    // pointer slots are filled per call; offsets go to the side record
+                    it.e.d = make_pass_desc(g, p, nullptr, ws[i], hs[i], ws[i], nullptr, c, nullptr, 0, INT_MAX,
+                                            base, sign, skip, 0, ra, rb);
+                    it.e.count = it.e.d.n_row_tiles * it.e.d.n_windows;
+                    it.e.dep = -1;
+                    it.r.img = i;
+                    it.r.src_is_ws = p > 0;
+                    it.r.src_off = p > 0 ? (int64_t)g.band_byte_off[p - 1] : 0;
+                    it.r.dst_is_ws = p + 1 < g.npass;
+                    it.r.dst_off = p + 1 < g.npass ? (int64_t)g.band_byte_off[p] : P->out_off[i] * esz;
+                    it.p = p;
+                    it.G = g.G[p];
+                    it.last = p + 1 == g.npass;
+                    items.push_back(it);
+                }
+            }
+        }
+        for (int p = 0; p < 4; ++p)
+            for (int G = kMaxG; G >= 3; --G)
+                for (int last = 0; last < 2; ++last) {
+                    BatchLaunch L{};
+                    L.first_group = (int)tmpl.size();
+                    int item = 0;
+                    for (const Item& it : items) {
+                        if (it.p != p || it.G != G || it.last != last) continue;
+                        EngineGroup e = it.e;
+                        e.first_item = item;
+                        item += e.count;
+                        tmpl.push_back(e);
+                        rel.push_back(it.r);
+                    }
+                    L.n_groups = (int)tmpl.size() - L.first_group;
+                    if (L.n_groups == 0) continue;
+                    L.n_items = item;
+                    L.G = G;
+                    L.first = p == 0;
+                    L.last = last != 0;
+                    P->launches.push_back(L);
+                }
+        i0 = i1;
+    }
+    P->n_groups = (int)tmpl.size();
+    P->table_bytes = (tmpl.size() * sizeof(EngineGroup) + 255) / 256 * 256;
+    // workspace: resolved table, then the bands of the largest chunk
+    for (auto& e : tmpl) (void)e;
+    for (BatchTemplate& r : rel) {
+        if (r.src_is_ws) r.src_off += (int64_t)P->table_bytes;
+        if (r.dst_is_ws) r.dst_off += (int64_t)P->table_bytes;
+    }
+    P->ws_bytes = P->table_bytes + band_peak;
+
+    hipError_t e = hipMalloc((void**)&P->d_tmpl, tmpl.size() * sizeof(EngineGroup));
+    if (e == hipSuccess) e = hipMalloc((void**)&P->d_rel, rel.size() * sizeof(BatchTemplate));
+    if (e == hipSuccess)
+        e = hipMemcpy(P->d_tmpl, tmpl.data(), tmpl.size() * sizeof(EngineGroup), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(P->d_rel, rel.data(), rel.size() * sizeof(BatchTemplate), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(P->d_tmpl);
+        hipFree(P->d_rel);
+        delete P;
+        return hip_fail(e, "batch plan tables");
+    }
+    *ws_bytes = P->ws_bytes;
+    *out_elems = P->out_elems;
+    if (out_offsets)
+        for (int i = 0; i < n; ++i) out_offsets[i] = P->out_off[i];
+    *plan = P;
+    return FHT_OK;
 }
-int fht_batch_forward(const fht_batch_plan*, const void* const*, void*, void*, size_t, void*)
+
+int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* hough, void* workspace, size_t ws_bytes,
+                      void* stream)
 {
-    return fht::fail(FHT_ERR_UNSUPPORTED, "batched forward not built yet");
+    if (!P || !imgs || !hough) return fail(FHT_ERR_INVALID, "null batch argument");
+    if (!workspace || ws_bytes < P->ws_bytes)
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", P->ws_bytes,
+                    workspace ? ws_bytes : 0);
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    EngineGroup* table = (EngineGroup*)workspace;
+    hipLaunchKernelGGL(fht_batch_fixup_kernel, dim3((P->n_groups + 255) / 256), dim3(256), 0, s, P->d_tmpl, P->d_rel,
+                       P->n_groups, imgs, (unsigned char*)hough, (unsigned char*)workspace, table);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batch fixup launch");
+    const int ti = P->in_t;
+    for (const BatchLaunch& L : P->launches) {
+        e = launch_table(table + L.first_group, L.n_groups, L.n_items, L.G, L.first, L.last, L.first ? ti : P->acc_t,
+                         P->acc_t, s);
+        if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    }
+    return FHT_OK;
 }
-int fht_batch_plan_destroy(fht_batch_plan*) { return FHT_OK; }
+
+int fht_batch_plan_destroy(fht_batch_plan* P)
+{
+    if (!P) return FHT_OK;
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev != P->device) hipSetDevice(P->device);
+    hipFree(P->d_tmpl);
+    hipFree(P->d_rel);
+    if (dev != P->device) hipSetDevice(dev);
+    delete P;
+    return FHT_OK;
 }
+
+}  // extern "C"

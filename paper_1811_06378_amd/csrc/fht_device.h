@@ -1,30 +1,32 @@
 // Device code of the dyadic Fast Hough Transform for gfx950 (CDNA4): the
-// kernel templates, instantiated per element type in fht_inst_*.hip.
+// kernel templates, instantiated per element type in fht_fwd_*.hip and
+// fht_adj_*.hip.
 //
 // The transform of one quadrant is the stage recurrence of Brady's FHT
 // (arXiv 1811.06378, section 2 and section 4 / Fig. 6): after stage j the rows
 // form blocks of 2^(j+1); stage j merges two neighbouring blocks,
-//   A[j+1][b*2^(j+1) + t][x] = A[j][b*2^(j+1) + (t>>1)][x]
-//                            + A[j][b*2^(j+1) + 2^j + (t>>1)][x + dir*(t - (t>>1))]   (mod W).
+//   A[j+1][b*2^(j+1) + t][xi] = A[j][b*2^(j+1) + (t>>1)][xi]
+//                             + A[j][b*2^(j+1) + 2^j + (t>>1)][xi + (t - (t>>1))]   (mod W),
+// written in the quadrant's column coordinate xi = dir * x, in which every
+// quadrant's patterns lean the same way (quadrants 2 and 3 are mirrored).
 //
 // Stage fusion.  G consecutive stages starting at stage j0 regroup exactly:
 // with u < 2^j0, m, v < 2^G,
-//   A[j0+G][B*2^(j0+G) + u*2^G + v][x]
-//     = MiniFHT_G( m -> A[j0][B*2^(j0+G) + m*2^j0 + u][x + dir*u*m] )[v][x],
+//   A[j0+G][B*2^(j0+G) + u*2^G + v][xi]
+//     = MiniFHT_G( m -> A[j0][B*2^(j0+G) + m*2^j0 + u][xi + u*m] )[v][xi],
 // i.e. the same G-stage transform on the 2^G rows m*2^j0 + u, each read with a
-// per-row column offset dir*u*m.  Applied twice inside a tile (G = 3 + GB):
-// the first 3 stages run on 8 contiguous rows held by one wave, the last GB
-// stages on rows 8g + u' read back from LDS with offsets dir*u'*g.
+// per-row column offset u*m.  Applied twice inside a tile (G = 3 + GB): the
+// first 3 stages run on 8 contiguous rows held by one wave, the last GB stages
+// on rows 8g + u' read back from LDS with offsets u'*g.
 //
 // Register layout.  A workgroup (8 waves) holds 64 rows x 512 columns; a lane
 // owns 8 consecutive columns of 8 rows.  A stage's column shift (at most 4 in
 // registers) reads the lane's own registers or, across the lane boundary, the
-// neighbouring lane's registers through a DPP wavefront shift by one lane, so
-// the shift costs no LDS traffic.  The rightmost (leftmost for dir = -1)
-// 2^G - 1 columns of a tile are halo: computed, not stored.
+// next lane's registers through a DPP wavefront shift by one lane, so the
+// shift costs no LDS traffic.  The last 2^G - 1 columns of a tile are halo:
+// computed, not stored.
 //
 // No MFMA: the recurrence is a bandwidth-bound chain of additions.
-
 #pragma once
 
 #include "fht_internal.h"
@@ -34,14 +36,6 @@
 namespace fht {
 
 // ------------------------------------------------------------ small helpers
-
-__device__ __forceinline__ int wrap_once(int e, int W)
-{
-    // e in [0, W + 512): one conditional subtraction covers W >= 512
-    if (e >= W) e -= W;
-    if (e >= W) e %= W;
-    return e;
-}
 
 __device__ __forceinline__ int mod_pos(long long a, int W)
 {
@@ -80,16 +74,161 @@ template <typename T> __device__ __forceinline__ T to_acc(uint8_t v) { return (T
 template <typename T> __device__ __forceinline__ T to_acc(int v) { return (T)v; }
 template <typename T> __device__ __forceinline__ T to_acc(float v) { return (T)v; }
 
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// a mod W for a wave-uniform a (|a| < 4W whenever W >= 1024 in the pass
+// geometry; small W takes the division).
+__device__ __forceinline__ int mod_w(int a, int W)
+{
+    if (W >= 1024 && a > -4 * W && a < 4 * W) {
+        a += 4 * W;
+        if (a >= 4 * W) a -= 4 * W;
+        if (a >= 2 * W) a -= 2 * W;
+        if (a >= W) a -= W;
+        return a;
+    }
+    int r = a % W;
+    return r < 0 ? r + W : r;
+}
+
+// e in [0, W + 512) -> e mod W
+__device__ __forceinline__ int wrap_up(int e, int W)
+{
+    if (e >= W) e -= W;
+    if (e >= W) e %= W;
+    return e;
+}
+
+// e in (-512, W) -> e mod W
+__device__ __forceinline__ int wrap_down(int e, int W)
+{
+    if (e < 0) e += W;
+    if (e < 0) e = mod_pos(e, W);
+    return e;
+}
+
+// Memory start of the lane's 8-column run.  The lane's registers c = 0..7 hold
+// xi = xi0 + 8*lane + c.  Unmirrored, column x = xi + shift_x and the run
+// ascends from x(c=0); mirrored, x = -xi + shift_x, so register c sits at
+// run_start + 7 - c.
+__device__ __forceinline__ int lane_run_start(int xi0, int shift_x, int lane, int W, int mirror)
+{
+    if (!mirror) return wrap_up(mod_w(xi0 + shift_x, W) + 8 * lane, W);
+    return wrap_down(mod_w(-xi0 - 7 + shift_x, W) - 8 * lane, W);
+}
+
+// Column of register c for a run start (element patch paths).
+__device__ __forceinline__ int run_col(int start, int c, int W, int mirror)
+{
+    int e = start + (mirror ? 7 - c : c);
+    return e >= W ? e - W : e;
+}
+
+// ------------------------------------------------------------ vector access
+
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef int i32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef unsigned int u32x2u __attribute__((ext_vector_type(2), aligned(4)));
+
+template <typename T> struct vec4u;
+template <> struct vec4u<float> { typedef f32x4u type; };
+template <> struct vec4u<int> { typedef i32x4u type; };
+
+// 8 consecutive elements.  Only dword alignment is required: gfx950 serves
+// dword-aligned 16-byte vector accesses, which the pre-rolled rows need.
+template <typename T>
+__device__ __forceinline__ void load8(const T* p, T (&v)[8])
+{
+    typedef typename vec4u<T>::type V;
+    const V a = *reinterpret_cast<const V*>(p);
+    const V b = *reinterpret_cast<const V*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+template <typename T>
+__device__ __forceinline__ void store8(T* p, const T (&v)[8])
+{
+    typedef typename vec4u<T>::type V;
+    V a, b;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
+    *reinterpret_cast<V*>(p) = a;
+    *reinterpret_cast<V*>(p + 4) = b;
+}
+
+// Streaming store for the final Hough image (written once, never re-read here).
+template <typename T>
+__device__ __forceinline__ void store8_stream(T* p, const T (&v)[8])
+{
+    typedef typename vec4u<T>::type V;
+    V a, b;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
+    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<V*>(p + 4));
+}
+
+template <typename T>
+__device__ __forceinline__ void reverse8(T (&v)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const T t = v[c];
+        v[c] = v[7 - c];
+        v[7 - c] = t;
+    }
+}
+
+template <typename TIn>
+__device__ __forceinline__ bool vec_ok(const TIn* p)
+{
+    if constexpr (sizeof(TIn) == 1) return (reinterpret_cast<uintptr_t>(p) & 3) == 0;
+    else return true;
+}
+
+template <typename TIn, typename T>
+__device__ __forceinline__ void load8_src(const TIn* p, T (&v)[8])
+{
+    if constexpr (sizeof(TIn) == 1) {
+        const u32x2u w = *reinterpret_cast<const u32x2u*>(p);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            v[c] = (T)((w.x >> (8 * c)) & 0xFFu);
+            v[4 + c] = (T)((w.y >> (8 * c)) & 0xFFu);
+        }
+    } else {
+        load8<T>(reinterpret_cast<const T*>(p), v);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero8(T (&v)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = (T)0;
+}
+
+// Loads are issued for all rows before any result is used: lanes whose 8
+// columns lie inside the data read them with 16-byte loads, lanes whose 8
+// columns are all zero padding read a static zero page, and only lanes that
+// straddle a boundary (rare) are patched element by element afterwards.  An
+// if/else per row would make every row wait for the previous row's loads.
+static __device__ __attribute__((aligned(64))) unsigned int g_zero_page[16];
+
+template <typename T>
+__device__ __forceinline__ const T* zero_page()
+{
+    return reinterpret_cast<const T*>(g_zero_page);
+}
+
 // --------------------------------------------------------- register stages
 
-// Forward stage J on 8 register rows: blocks of 2^(J+1) rows, block rows
-// t = 0..2^(J+1)-1 from rows (t>>1) and 2^J + (t>>1), the latter shifted by
-// dir*(t - (t>>1)) columns.
-// Forward stage J on 8 register rows: blocks of 2^(J+1) rows; block rows
-// 2i and 2i+1 both come from the pair (top row i, bottom row 2^J + i), the
-// bottom one shifted by dir*i and dir*(i+1) columns.  Each output pair
-// depends on one input pair only, so the stage is a set of row butterflies.
-template <typename T, int DIR, int J>
+// Forward stage J on 8 register rows: blocks of 2^(J+1) rows; block rows 2i
+// and 2i+1 both come from the pair (top row i, bottom row 2^J + i), the
+// bottom one shifted by i and i+1 columns.  Each output pair depends on one
+// input pair only: the stage is a set of row butterflies.
+template <typename T, int J>
 __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
 {
     constexpr int H = 1 << J;
@@ -98,20 +237,13 @@ __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
     for (int blk = 0; blk < 8; blk += 2 * H) {
 #pragma unroll
         for (int i = 0; i < H; ++i) {
-            const T (&top)[8] = a[blk + i];
-            const T (&bot)[8] = a[blk + H + i];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                int c0 = c + DIR * i, c1 = c + DIR * (i + 1);
-                T b0, b1;
-                if (c0 >= 8) b0 = dpp_move<kDppFromNext>(bot[c0 - 8]);
-                else if (c0 < 0) b0 = dpp_move<kDppFromPrev>(bot[c0 + 8]);
-                else b0 = bot[c0];
-                if (c1 >= 8) b1 = dpp_move<kDppFromNext>(bot[c1 - 8]);
-                else if (c1 < 0) b1 = dpp_move<kDppFromPrev>(bot[c1 + 8]);
-                else b1 = bot[c1];
-                o[blk + 2 * i][c] = top[c] + b0;
-                o[blk + 2 * i + 1][c] = top[c] + b1;
+                const int c0 = c + i, c1 = c + i + 1;
+                const T b0 = c0 >= 8 ? dpp_move<kDppFromNext>(a[blk + H + i][c0 - 8]) : a[blk + H + i][c0];
+                const T b1 = c1 >= 8 ? dpp_move<kDppFromNext>(a[blk + H + i][c1 - 8]) : a[blk + H + i][c1];
+                o[blk + 2 * i][c] = a[blk + i][c] + b0;
+                o[blk + 2 * i + 1][c] = a[blk + i][c] + b1;
             }
         }
     }
@@ -123,9 +255,9 @@ __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
 
 // Transpose of fwd_stage: input row t of a merged block goes back to the two
 // rows it was summed from, so
-//   top[i][x]    = g[2i][x] + g[2i+1][x]
-//   bottom[u][x] = g[2u][x - dir*u] + g[2u+1][x - dir*(u+1)].
-template <typename T, int DIR, int J>
+//   top[i][xi]    = g[2i][xi] + g[2i+1][xi]
+//   bottom[u][xi] = g[2u][xi - u] + g[2u+1][xi - u - 1].
+template <typename T, int J>
 __device__ __forceinline__ void adj_stage(T (&a)[8][8])
 {
     constexpr int H = 1 << J;
@@ -141,19 +273,9 @@ __device__ __forceinline__ void adj_stage(T (&a)[8][8])
         for (int u = 0; u < H; ++u) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                T x0, x1;
-                {
-                    const int cc = c - DIR * u;
-                    if (cc >= 8) x0 = dpp_move<kDppFromNext>(a[blk + 2 * u][cc - 8]);
-                    else if (cc < 0) x0 = dpp_move<kDppFromPrev>(a[blk + 2 * u][cc + 8]);
-                    else x0 = a[blk + 2 * u][cc];
-                }
-                {
-                    const int cc = c - DIR * (u + 1);
-                    if (cc >= 8) x1 = dpp_move<kDppFromNext>(a[blk + 2 * u + 1][cc - 8]);
-                    else if (cc < 0) x1 = dpp_move<kDppFromPrev>(a[blk + 2 * u + 1][cc + 8]);
-                    else x1 = a[blk + 2 * u + 1][cc];
-                }
+                const int c0 = c - u, c1 = c - u - 1;
+                const T x0 = c0 < 0 ? dpp_move<kDppFromPrev>(a[blk + 2 * u][c0 + 8]) : a[blk + 2 * u][c0];
+                const T x1 = c1 < 0 ? dpp_move<kDppFromPrev>(a[blk + 2 * u + 1][c1 + 8]) : a[blk + 2 * u + 1][c1];
                 o[blk + H + u][c] = x0 + x1;
             }
         }
@@ -164,21 +286,23 @@ __device__ __forceinline__ void adj_stage(T (&a)[8][8])
         for (int c = 0; c < 8; ++c) a[r][c] = o[r][c];
 }
 
-template <typename T, int DIR, int GB>
+template <typename T, int GB>
 __device__ __forceinline__ void fwd_stages_b(T (&b)[8][8])
 {
-    if constexpr (GB > 0) fwd_stage<T, DIR, 0>(b);
-    if constexpr (GB > 1) fwd_stage<T, DIR, 1>(b);
-    if constexpr (GB > 2) fwd_stage<T, DIR, 2>(b);
+    if constexpr (GB > 0) fwd_stage<T, 0>(b);
+    if constexpr (GB > 1) fwd_stage<T, 1>(b);
+    if constexpr (GB > 2) fwd_stage<T, 2>(b);
 }
 
-template <typename T, int DIR, int GB>
+template <typename T, int GB>
 __device__ __forceinline__ void adj_stages_b(T (&b)[8][8])
 {
-    if constexpr (GB > 2) adj_stage<T, DIR, 2>(b);
-    if constexpr (GB > 1) adj_stage<T, DIR, 1>(b);
-    if constexpr (GB > 0) adj_stage<T, DIR, 0>(b);
+    if constexpr (GB > 2) adj_stage<T, 2>(b);
+    if constexpr (GB > 1) adj_stage<T, 1>(b);
+    if constexpr (GB > 0) adj_stage<T, 0>(b);
 }
+
+// ------------------------------------------------------------------ LDS
 
 // LDS rows are column-swizzled: column x lives in plane (x & 7) at slot
 // (x >> 3), so lane-contiguous 8-column groups and offset reads both spread
@@ -232,177 +356,53 @@ __device__ __forceinline__ void lds_write8(T* row_lane, int off, const T (&v)[8]
     }
 }
 
-__device__ __forceinline__ int lds_index(int tile_row, int col)
-{
-    // column-swizzled: column col of a row lives in plane (col & 7) at (col >> 3),
-    // so both the lane-contiguous stores and the offset loads hit 64 distinct banks
-    return tile_row * kLdsRow + (col & 7) * kPlane + (col >> 3);
-}
-
-// ------------------------------------------------------------ vector access
-
-typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
-typedef int i32x4u __attribute__((ext_vector_type(4), aligned(4)));
-typedef unsigned int u32x2u __attribute__((ext_vector_type(2), aligned(4)));
-
-template <typename T> struct vec4u;
-template <> struct vec4u<float> { typedef f32x4u type; };
-template <> struct vec4u<int> { typedef i32x4u type; };
-
-// 8 consecutive elements.  Only dword alignment is required: gfx950 serves
-// dword-aligned 16-byte vector accesses, which the pre-rolled rows need.
-template <typename T>
-__device__ __forceinline__ void load8(const T* p, T (&v)[8])
-{
-    typedef typename vec4u<T>::type V;
-    const V a = *reinterpret_cast<const V*>(p);
-    const V b = *reinterpret_cast<const V*>(p + 4);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-
-template <typename T>
-__device__ __forceinline__ void store8(T* p, const T (&v)[8])
-{
-    typedef typename vec4u<T>::type V;
-    V a, b;
-    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
-    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
-    *reinterpret_cast<V*>(p) = a;
-    *reinterpret_cast<V*>(p + 4) = b;
-}
-
-// Streaming store for the final Hough image (written once, never re-read here).
-template <typename T>
-__device__ __forceinline__ void store8_stream(T* p, const T (&v)[8])
-{
-    typedef typename vec4u<T>::type V;
-    V a, b;
-    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
-    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
-    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
-    __builtin_nontemporal_store(b, reinterpret_cast<V*>(p + 4));
-}
-
-template <typename TIn>
-__device__ __forceinline__ bool vec_ok(const TIn* p)
-{
-    if constexpr (sizeof(TIn) == 1) return (reinterpret_cast<uintptr_t>(p) & 3) == 0;
-    else return true;
-}
-
-template <typename TIn, typename T>
-__device__ __forceinline__ void load8_src(const TIn* p, T (&v)[8])
-{
-    if constexpr (sizeof(TIn) == 1) {
-        const u32x2u w = *reinterpret_cast<const u32x2u*>(p);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            v[c] = (T)((w.x >> (8 * c)) & 0xFFu);
-            v[4 + c] = (T)((w.y >> (8 * c)) & 0xFFu);
-        }
-    } else {
-        load8<T>(reinterpret_cast<const T*>(p), v);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void zero8(T (&v)[8])
-{
-#pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = (T)0;
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// a mod W for a wave-uniform a (the pass geometry keeps |a| < 4W whenever
-// W >= 1024; small W takes the division).
-__device__ __forceinline__ int mod_w(int a, int W)
-{
-    if (W >= 1024 && a > -4 * W && a < 4 * W) {
-        a += 4 * W;
-        if (a >= 4 * W) a -= 4 * W;
-        if (a >= 2 * W) a -= 2 * W;
-        if (a >= W) a -= W;
-        return a;
-    }
-    int r = a % W;
-    return r < 0 ? r + W : r;
-}
-
-// e in [0, W + 512) -> e mod W
-__device__ __forceinline__ int wrap_lane(int e, int W)
-{
-    if (e >= W) e -= W;
-    if (e >= W) e %= W;
-    return e;
-}
-
 // ------------------------------------------------------------ source loads
-//
-// Loads are issued for all rows before any result is used: lanes whose 8
-// columns lie inside the data read them with two 16-byte loads, lanes whose 8
-// columns are all zero padding read a static zero page, and only lanes that
-// straddle a boundary (rare) are patched element by element afterwards.  An
-// if/else per row would make every row wait for the previous row's loads.
 
-static __device__ __attribute__((aligned(64))) unsigned int g_zero_page[16];
-
+// Band row at xi = xrow + 8*lane + c (band index = (xi + src_off) mod W).
 template <typename T>
-__device__ __forceinline__ const T* zero_page()
+__device__ __forceinline__ bool issue_band_row(const T* band_row, int src_off, int src_bw, int W, int xrow, int lane,
+                                               T (&v)[8], int& e0)
 {
-    return reinterpret_cast<const T*>(g_zero_page);
-}
-
-// Band row R: returns the lane's first band index and whether it needs a patch.
-template <typename T>
-__device__ __forceinline__ bool issue_band_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
-{
-    const int W = d.W;
-    const T* band = reinterpret_cast<const T*>(d.src) + (long long)R * d.src_ld;
-    e0 = wrap_lane(mod_w(xrow + d.src_off, W) + 8 * lane, W);
-    const bool fast = e0 + 8 <= d.src_bw;
-    const bool zero = e0 >= d.src_bw && e0 + 8 <= W;
-    load8<T>(fast ? band + e0 : zero_page<T>(), v);
+    e0 = wrap_up(mod_w(xrow + src_off, W) + 8 * lane, W);
+    const bool fast = e0 + 8 <= src_bw;
+    const bool zero = e0 >= src_bw && e0 + 8 <= W;
+    load8<T>(fast ? band_row + e0 : zero_page<T>(), v);
     return !fast && !zero;
 }
 
 template <typename T>
-__device__ __forceinline__ void patch_band_row(const PassDesc& d, int R, int e0, T (&v)[8])
+__device__ __forceinline__ void patch_band_row(const T* band_row, int src_bw, int W, int e0, T (&v)[8])
 {
-    const int W = d.W;
-    const T* band = reinterpret_cast<const T*>(d.src) + (long long)R * d.src_ld;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         int e = e0 + c;
         if (e >= W) e -= W;
-        v[c] = (e < d.src_bw) ? band[e] : (T)0;
+        v[c] = (e < src_bw) ? band_row[e] : (T)0;
     }
 }
 
-// Image row R (quadrants 1, 2; sheared for the angle range).
+// Image row R of quadrants 1, 2 (x = +-xi, sheared for the angle range).
 template <typename TIn, typename T>
 __device__ __forceinline__ bool issue_image_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
 {
     const int W = d.W;
     const TIn* p = reinterpret_cast<const TIn*>(d.src) + (long long)R * d.src_ld;
-    e0 = wrap_lane(mod_w(xrow - shear_of_row(R, d.S1, d.n), W) + 8 * lane, W);
+    e0 = lane_run_start(xrow, -shear_of_row(R, d.S1, d.n), lane, W, d.mirror);
     const bool row_ok = R < d.img_h;
     const bool fast = row_ok && e0 + 8 <= d.img_w && vec_ok<TIn>(p + e0);
     const bool zero = !row_ok || (e0 >= d.img_w && e0 + 8 <= W);
     load8_src<TIn, T>(fast ? p + e0 : zero_page<TIn>(), v);
+    if (d.mirror) reverse8(v);
     return !fast && !zero;
 }
 
 template <typename TIn, typename T>
 __device__ __forceinline__ void patch_image_row(const PassDesc& d, int R, int e0, T (&v)[8])
 {
-    const int W = d.W;
     const TIn* img = reinterpret_cast<const TIn*>(d.src);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        int e = e0 + c;
-        if (e >= W) e -= W;
+        const int e = run_col(e0, c, d.W, d.mirror);
         if (d.src_kind == SRC_IMAGE)
             v[c] = (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + e]) : (T)0;
         else
@@ -410,11 +410,11 @@ __device__ __forceinline__ void patch_image_row(const PassDesc& d, int R, int e0
     }
 }
 
-// Transposed image (quadrants 3, 4) with a shear: element loads only.
+// Transposed image with a shear: element loads only.
 template <typename TIn, typename T>
 __device__ __forceinline__ bool issue_image_t_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
 {
-    e0 = wrap_lane(mod_w(xrow - shear_of_row(R, d.S1, d.n), d.W) + 8 * lane, d.W);
+    e0 = lane_run_start(xrow, -shear_of_row(R, d.S1, d.n), lane, d.W, d.mirror);
     zero8(v);
     return true;
 }
@@ -425,109 +425,43 @@ template <typename TIn, typename T>
 __device__ __forceinline__ void load_rows_transposed(const PassDesc& d, int R0, int xrow, int lane, T (&a)[8][8])
 {
     const int W = d.W;
-    const int e0 = wrap_lane(mod_w(xrow, W) + 8 * lane, W);
+    const int e0 = lane_run_start(xrow, 0, lane, W, d.mirror);
     const TIn* img = reinterpret_cast<const TIn*>(d.src);
     const bool all_cols = R0 + 8 <= d.img_w;
-    T t[8][8];
-    bool patch[8];
-    bool any = false;
+    unsigned patch = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        int e = e0 + c;
-        if (e >= W) e -= W;
+        const int e = run_col(e0, c, W, d.mirror);
         const TIn* p = img + (long long)e * d.src_ld + R0;
         const bool inside = e < d.img_h;
         const bool fast = inside && all_cols && vec_ok<TIn>(p);
-        load8_src<TIn, T>(fast ? p : zero_page<TIn>(), t[c]);
-        patch[c] = inside && !fast;
-        any |= patch[c];
+        T t[8];
+        load8_src<TIn, T>(fast ? p : zero_page<TIn>(), t);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r][c] = t[r];
+        if (inside && !fast) patch |= 1u << c;
     }
-    if (__any(any)) {
+    if (__any(patch != 0)) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            if (patch[c]) {
-                int e = e0 + c;
-                if (e >= W) e -= W;
+            if (patch & (1u << c)) {
+                const int e = run_col(e0, c, W, d.mirror);
                 const TIn* p = img + (long long)e * d.src_ld + R0;
 #pragma unroll
-                for (int r = 0; r < 8; ++r) t[c][r] = (R0 + r < d.img_w) ? to_acc<T>(p[r]) : (T)0;
+                for (int r = 0; r < 8; ++r) a[r][c] = (R0 + r < d.img_w) ? to_acc<T>(p[r]) : (T)0;
             }
         }
     }
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) a[r][c] = t[c][r];
 }
 
 // ------------------------------------------------------ fused forward pass
 
-template <typename TIn, typename T, int GB, int DIR, bool FIRST, bool LAST>
-__device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* lds)
+// Phase B of a forward tile for GB = G - 3 stages after the exchange.  The
+// exchange runs in two halves (registers 0-3, then 4-7 of every wave) so the
+// LDS holds 32 rows and two workgroups fit on a CU.
+template <typename T, int GB>
+__device__ __forceinline__ void fwd_phase_b(T (&a)[8][8], T (&b)[8][8], T* lds, int wave, int lane)
 {
-    constexpr int G = 3 + GB;
-    constexpr int NMINI = 1 << (6 - G);          // mini-transforms of 2^G rows per tile
-    constexpr int VW = kWinCols - (1 << G);      // stored columns per tile
-    constexpr int LOFF = DIR > 0 ? 0 : kLdsOffNeg;
-    const int lane = threadIdx.x & 63;
-    const int wave = uniform(threadIdx.x >> 6);
-    const int j0 = d.j0;
-    const int n_mini = d.n >> G;
-    const int x_lo = d.x_start + win * VW;
-    const int xw0 = x_lo - (DIR < 0 ? (1 << G) : 0);
-
-    // ---- phase A: 8 contiguous mini rows per wave, first 3 stages
-    T a[8][8];
-    {
-        const int tr0 = wave * 8;
-        const int t = tr0 >> G;
-        const int mu = rt * NMINI + t;
-        const int B = mu >> j0;
-        const int u = mu & ((1 << j0) - 1);
-        const bool active = (mu < n_mini) && ((u << G) <= d.row_limit);
-        if (!active) {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) zero8(a[r]);
-        } else if (FIRST && d.src_kind == SRC_IMAGE_T && d.S1 == 0) {
-            // first pass (u = 0): the wave's rows are 8 consecutive image columns
-            load_rows_transposed<TIn, T>(d, (B << G) + (tr0 & ((1 << G) - 1)), xw0, lane, a);
-        } else {
-            int e0[8];
-            bool patch[8];
-            bool any = false;
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int m = (tr0 + r) & ((1 << G) - 1);
-                const int R = (B << (j0 + G)) + (m << j0) + u;
-                if constexpr (FIRST) {
-                    patch[r] = d.src_kind == SRC_IMAGE ? issue_image_row<TIn, T>(d, R, xw0, lane, a[r], e0[r])
-                                                       : issue_image_t_row<TIn, T>(d, R, xw0, lane, a[r], e0[r]);
-                } else {
-                    patch[r] = issue_band_row<T>(d, R, xw0 + DIR * u * m, lane, a[r], e0[r]);
-                }
-                any |= patch[r];
-            }
-            if (__any(any)) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    if (patch[r]) {
-                        const int m = (tr0 + r) & ((1 << G) - 1);
-                        const int R = (B << (j0 + G)) + (m << j0) + u;
-                        if constexpr (FIRST) patch_image_row<TIn, T>(d, R, e0[r], a[r]);
-                        else patch_band_row<T>(d, R, e0[r], a[r]);
-                    }
-                }
-            }
-        }
-    }
-    fwd_stage<T, DIR, 0>(a);
-    fwd_stage<T, DIR, 1>(a);
-    fwd_stage<T, DIR, 2>(a);
-
-    // ---- phase B: rows 8g + u' with offsets dir*u'*g, last GB stages.  The
-    // exchange runs in two halves (registers 0-3, then 4-7 of every wave) so
-    // the LDS holds 32 rows and two workgroups fit on a CU.
-    T b[8][8];
     if constexpr (GB == 0) {
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -538,8 +472,8 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             {
-                // column 8*lane + c + LOFF of LDS row wave*4 + rr: plane c, slot lane + LOFF/8
-                T* lw = lds + wave * 4 * kLdsRow + lane + LOFF / 8;
+                // column 8*lane + c of LDS row wave*4 + rr: plane c, slot lane
+                T* lw = lds + wave * 4 * kLdsRow + lane;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
@@ -554,21 +488,99 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                     const int kappa = (wave << (3 - GB)) + q;
                     const int t = kappa >> 3;
                     const int up = kappa & 7;
-                    const int wa = (t << GB) + rp;         // phase-A wave holding the row
-                    const int off = uniform(DIR * up * rp + LOFF);
-                    lds_read8<T>(lds + (wa * 4 + (up & 3)) * kLdsRow + lane, off, b[rho]);
+                    const int wa = (t << GB) + rp;  // phase-A wave holding the row
+                    lds_read8<T>(lds + (wa * 4 + (up & 3)) * kLdsRow + lane, uniform(up * rp), b[rho]);
                 }
             }
             if (h == 0) __syncthreads();
         }
+        fwd_stages_b<T, GB>(b);
     }
-    fwd_stages_b<T, DIR, GB>(b);
+}
+
+// One tile (64 rows x 512 columns) of one forward pass of G = 3 + GB stages.
+// rt: row tile, win: column window.  Every thread of the workgroup calls it.
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
+__device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* lds)
+{
+    constexpr int G = 3 + GB;
+    constexpr int VW = kWinCols - (1 << G);      // stored columns per tile
+    constexpr int NMINI = 1 << (6 - G);          // mini-transforms of 2^G rows per tile
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform(threadIdx.x >> 6);
+    const int j0 = d.j0;
+    const int n_mini = d.n >> G;                 // mini-transforms in the quadrant
+    const int xi0 = d.x_start + win * VW;        // xi of the tile's column 0
+
+    // A last-pass tile lying wholly in the black zone of every one of its rows
+    // (section 3.2, case c) is written as zeros without loading anything.
+    bool black = false;
+    if (LAST && d.black_ok) {
+        const int s_max = min(rt * 64 + 63, d.n - 1);
+        black = xi0 >= d.black_lo && xi0 + VW <= d.black_lo + d.n - s_max;
+    }
+
+    T b[8][8];
+    if (black) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) zero8(b[r]);
+    } else {
+        // ---- phase A: 8 contiguous mini rows per wave, first 3 stages
+        T a[8][8];
+        const int tr0 = wave * 8;
+        const int t = tr0 >> G;
+        const int mu = rt * NMINI + t;
+        const int B = mu >> j0;
+        const int u = mu & ((1 << j0) - 1);
+        const bool active = (mu < n_mini) && ((u << G) <= d.row_limit);
+        if (!active) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) zero8(a[r]);
+        } else if (FIRST && d.src_kind == SRC_IMAGE_T && d.S1 == 0) {
+            // first pass (u = 0): the wave's rows are 8 consecutive image columns
+            load_rows_transposed<TIn, T>(d, (B << G) + (tr0 & ((1 << G) - 1)), xi0, lane, a);
+        } else {
+            int e0[8];
+            bool patch[8];
+            bool any = false;
+            const T* band = reinterpret_cast<const T*>(d.src);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int m = (tr0 + r) & ((1 << G) - 1);
+                const int R = (B << (j0 + G)) + (m << j0) + u;
+                if constexpr (FIRST) {
+                    patch[r] = d.src_kind == SRC_IMAGE ? issue_image_row<TIn, T>(d, R, xi0, lane, a[r], e0[r])
+                                                       : issue_image_t_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
+                } else {
+                    patch[r] = issue_band_row<T>(band + (long long)R * d.src_ld, d.src_off, d.src_bw, d.W,
+                                                 xi0 + u * m, lane, a[r], e0[r]);
+                }
+                any |= patch[r];
+            }
+            if (__any(any)) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    if (patch[r]) {
+                        const int m = (tr0 + r) & ((1 << G) - 1);
+                        const int R = (B << (j0 + G)) + (m << j0) + u;
+                        if constexpr (FIRST) patch_image_row<TIn, T>(d, R, e0[r], a[r]);
+                        else patch_band_row<T>(band + (long long)R * d.src_ld, d.src_bw, d.W, e0[r], a[r]);
+                    }
+                }
+            }
+        }
+        fwd_stage<T, 0>(a);
+        fwd_stage<T, 1>(a);
+        fwd_stage<T, 2>(a);
+        // ---- phase B: rows 8g + u' read with offsets u'*g, last GB stages
+        fwd_phase_b<T, GB>(a, b, lds, wave, lane);
+    }
 
     // ---- store
     const int wc0 = 8 * lane;
-    const bool lane_ok = DIR > 0 ? (wc0 < VW) : (wc0 >= (1 << G));
-    if (!lane_ok) return;
-    const int x0 = xw0 + wc0;
+    if (wc0 >= VW) return;
+    const int xi = xi0 + wc0;  // xi of register 0
+    const int W = d.W;
 #pragma unroll
     for (int rho = 0; rho < 8; ++rho) {
         const int rp = rho & ((1 << GB) - 1);
@@ -585,7 +597,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         const int out_row = (B << (j0 + G)) + s_local;
         if constexpr (!LAST) {
             T* dst = reinterpret_cast<T*>(d.dst) + (long long)out_row * d.dst_ld;
-            const int e0 = x0 + d.dst_off;
+            const int e0 = xi + d.dst_off;
             if (e0 + 8 <= d.dst_bw) {
                 store8<T>(dst + e0, b[rho]);
             } else {
@@ -595,77 +607,178 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
             }
         } else {
             const int s = out_row;
-            if (s == d.skip_row) continue;
+            if (s == d.skip_row || xi >= W) continue;
             T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
             const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
-            const int W = d.W;
-            if (x0 >= W) continue;
-            const int xr = wrap_lane(x0 + roll, W);
-            if (x0 + 8 <= W && xr + 8 <= W) {
-                store8_stream<T>(dst + xr, b[rho]);
+            // memory run of the lane's 8 columns (descending for mirrored quadrants)
+            const int e0 = d.mirror ? wrap_down(mod_w(-xi - 7 + roll, W), W) : wrap_up(mod_w(xi + roll, W), W);
+            if (xi + 8 <= W && e0 + 8 <= W) {
+                T v[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v[c] = d.mirror ? b[rho][7 - c] : b[rho][c];
+                if (d.stream_store) store8_stream<T>(dst + e0, v);
+                else store8<T>(dst + e0, v);
             } else {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    if (x0 + c < W) {
-                        int e = xr + c;
-                        if (e >= W) e -= W;
-                        dst[e] = b[rho][c];
-                    }
-                }
+                for (int c = 0; c < 8; ++c)
+                    if (xi + c < W) dst[run_col(e0, c, W, d.mirror)] = b[rho][c];
             }
         }
     }
+}
+
+// Tile order.  Workgroups are dispatched to the 8 XCDs round-robin by block
+// index; numbering the tiles so that each XCD receives a contiguous run of
+// them keeps neighbouring windows (which share 2^G - 1 halo columns) and
+// neighbouring row tiles in one L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_tile(int block, int n_tiles)
+{
+    const int per = (n_tiles + kXcds - 1) / kXcds;
+    return (block % kXcds) * per + block / kXcds;
 }
 
 template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch L)
 {
     __shared__ T lds[kTileRows / 2 * kLdsRow];
-    const PassDesc& d = L.d[blockIdx.z];
-    if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
-    if (d.dir > 0) fwd_tile<TIn, T, GB, 1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
-    else fwd_tile<TIn, T, GB, -1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
-}
-
-// -------------------------------------------- direct form for n <= 4 rows
-
-template <typename TIn, typename T>
-__device__ __forceinline__ T src_value(const PassDesc& d, int R, int x)
-{
-    const int W = d.W;
-    const int e = mod_pos((long long)x - shear_of_row(R, d.S1, d.n), W);
-    const TIn* img = reinterpret_cast<const TIn*>(d.src);
-    if (d.src_kind == SRC_IMAGE)
-        return (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + e]) : (T)0;
-    return (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)e * d.src_ld + R]) : (T)0;
-}
-
-// The same add tree as K stages of the recurrence, evaluated top-down.
-template <typename TIn, typename T, int K>
-__device__ T direct_sum(const PassDesc& d, int base, int s, int x)
-{
-    if constexpr (K == 0) {
-        return src_value<TIn, T>(d, base, x);
-    } else {
-        const int sub = s >> 1;
-        const T top = direct_sum<TIn, T, K - 1>(d, base, sub, x);
-        const T bot = direct_sum<TIn, T, K - 1>(d, base + (1 << (K - 1)), sub,
-                                               mod_pos((long long)x + d.dir * (s - sub), d.W));
-        return top + bot;
+    int t = xcd_tile(blockIdx.x, L.n_tiles);
+    if (t >= L.n_tiles) return;
+    int z = 0;
+    while (z + 1 < L.nd && t >= L.d[z].n_row_tiles * L.d[z].n_windows) {
+        t -= L.d[z].n_row_tiles * L.d[z].n_windows;
+        ++z;
     }
+    const PassDesc& d = L.d[z];
+    const int rt = t / d.n_windows;
+    fwd_tile<TIn, T, GB, FIRST, LAST>(d, rt, t - rt * d.n_windows, lds);
 }
 
-template <typename TIn, typename T, int K>
-__global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
+// Many passes (of many images) of one kind in one launch: block -> item ->
+// group through the groups' first_item prefix, as in the engine queue.
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kThreads, 4) void fht_table_kernel(const EngineGroup* __restrict__ table, int n_groups,
+                                                                 int n_items)
 {
-    const PassDesc& d = L.d[blockIdx.z];
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (x >= d.W || s >= d.n || s > d.row_limit || s == d.skip_row) return;
-    const T v = direct_sum<TIn, T, K>(d, 0, s, x);
-    T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
-    const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
-    dst[mod_pos((long long)x + roll, d.W)] = v;
+    __shared__ T lds[kTileRows / 2 * kLdsRow];
+    const int item = xcd_tile(blockIdx.x, n_items);
+    if (item >= n_items) return;
+    int lo = 0, hi = n_groups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].first_item <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const EngineGroup& E = table[uniform(lo)];
+    const int local = item - E.first_item;
+    const int rt = local / E.d.n_windows;
+    fwd_tile<TIn, T, GB, FIRST, LAST>(E.d, rt, local - rt * E.d.n_windows, lds);
+}
+
+// ------------------------------------------------- persistent forward engine
+//
+// One launch runs every tile of every pass of one depth G = 3 + GB (of every
+// quadrant and image): an
+// ordered queue of items, each one tile of one group.  Items are taken in
+// queue order, so when a workgroup waits for the items of an earlier group,
+// each of those items is already held by a running workgroup that never
+// waits on a later item: the wait always ends.  A bounded spin turns a wait
+// that does not end (a planner error) into an error flag instead of a hang.
+
+__device__ __forceinline__ void wait_group(const unsigned* done, unsigned target, int limit, unsigned* err,
+                                           int agent_acquire)
+{
+    int it = 0;
+    while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(4);
+        if (++it > limit) {
+            __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
+    // The producers wrote their band rows back to memory before counting
+    // (release at agent scope).  An agent-scope acquire also invalidates this
+    // XCD's caches; the lighter form relies on no cache of this launch holding
+    // a line of the band before its group completed (bands are read only
+    // after completion, and a launch starts with invalidated caches).
+    if (agent_acquire) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool INLINE>
+__device__ __forceinline__ const EngineGroup& engine_group(const EngineArgs& A, int g)
+{
+    if constexpr (INLINE) return A.g[g];
+    else return A.table[g];
+}
+
+template <bool INLINE>
+__device__ __forceinline__ int engine_find(const EngineArgs& A, int item)
+{
+    // last group whose first_item <= item
+    int lo = 0, hi = A.n_groups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (engine_group<INLINE>(A, mid).first_item <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// INLINE: the groups travel in the kernel arguments (single images);
+// otherwise they are read from a device table (batched plans).
+template <typename TIn, typename T, int GB, bool INLINE>
+__global__ __launch_bounds__(kThreads, 4) void fht_engine_kernel(const EngineArgs A)
+{
+    __shared__ T lds[kTileRows / 2 * kLdsRow];
+    __shared__ int s_item;
+    unsigned* head = A.sync;
+    unsigned* err = A.sync + 1;
+    unsigned* done = A.sync + 2;
+    int seen_dep = -1;  // a dependency this workgroup has already seen complete
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    int item = uniform(s_item);
+    __syncthreads();
+    for (;;) {
+        if (item >= A.total_items) break;
+        // take the next item now; its latency hides behind this tile
+        unsigned next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(head, 1u);
+        const int g = uniform(engine_find<INLINE>(A, item));
+        const EngineGroup& E = engine_group<INLINE>(A, g);
+        const int local = item - E.first_item;
+        const int nw = E.d.n_windows;
+        const int rt = local / nw;
+        const int win = local - rt * nw;
+        const int dep = E.dep;
+        if (dep >= 0 && dep != seen_dep) {
+            if (threadIdx.x == 0) wait_group(done + dep, (unsigned)E.dep_count, A.spin_limit, err, A.agent_acquire);
+            __syncthreads();
+            seen_dep = dep;
+        }
+        if (E.d.src_kind != SRC_BAND) {
+            if (E.d.dst_kind == DST_HOUGH) fwd_tile<TIn, T, GB, true, true>(E.d, rt, win, lds);
+            else fwd_tile<TIn, T, GB, true, false>(E.d, rt, win, lds);
+        } else {
+            if (E.d.dst_kind == DST_HOUGH) fwd_tile<TIn, T, GB, false, true>(E.d, rt, win, lds);
+            else fwd_tile<TIn, T, GB, false, false>(E.d, rt, win, lds);
+        }
+        if (E.notify) {
+            // every wave's stores complete, then one release makes them visible
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __atomic_thread_fence(__ATOMIC_RELEASE);
+                __hip_atomic_fetch_add(done + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (threadIdx.x == 0) s_item = (int)next;
+        __syncthreads();
+        item = uniform(s_item);
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------ fused adjoint pass
@@ -674,53 +787,30 @@ __global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
 // read contiguously, the mini transform runs backwards (last GB stages
 // transposed, then the LDS exchange with offsets moved to the write side, then
 // the first 3 stages transposed) and row m is written with its column offset
-// dir*u*m added.
+// u*m added.  The halo sits at the low end of the tile.
 
-// Source row of an adjoint pass (Hough gradient or band), issue + patch as
-// for the forward loads.
-template <typename T, bool FROM_HOUGH>
-__device__ __forceinline__ bool adj_issue_row(const AdjDesc& d, int s_row, int xrow, int lane, T (&v)[8], int& e0)
+// Hough gradient row (first adjoint pass): quadrant row s -> Hough row, x =
+// +-xi, rolled columns.
+template <typename T>
+__device__ __forceinline__ bool adj_issue_hough(const AdjDesc& d, int s_row, int xrow, int lane, T (&v)[8], int& e0)
 {
     const int W = d.W;
-    if constexpr (!FROM_HOUGH) {
-        const T* band = reinterpret_cast<const T*>(d.src) + (long long)s_row * d.src_ld;
-        e0 = wrap_lane(mod_w(xrow + d.src_off, W) + 8 * lane, W);
-        const bool fast = e0 + 8 <= d.src_bw;
-        const bool zero = e0 >= d.src_bw && e0 + 8 <= W;
-        load8<T>(fast ? band + e0 : zero_page<T>(), v);
-        return !fast && !zero;
-    } else {
-        const bool skip = s_row == d.skip_row;
-        const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
-        const int roll = d.shifted ? ((d.roll_a + d.roll_b * s_row) >> 1) : 0;
-        e0 = wrap_lane(mod_w(xrow + roll, W) + 8 * lane, W);
-        const bool fast = !skip && e0 + 8 <= W;
-        load8<T>(fast ? src + e0 : zero_page<T>(), v);
-        return !skip && !fast;
-    }
+    const bool skip = s_row == d.skip_row;
+    const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
+    const int roll = d.shifted ? ((d.roll_a + d.roll_b * s_row) >> 1) : 0;
+    e0 = lane_run_start(xrow, roll, lane, W, d.mirror);
+    const bool fast = !skip && e0 + 8 <= W;
+    load8<T>(fast ? src + e0 : zero_page<T>(), v);
+    if (d.mirror) reverse8(v);
+    return !skip && !fast;
 }
 
-template <typename T, bool FROM_HOUGH>
-__device__ __forceinline__ void adj_patch_row(const AdjDesc& d, int s_row, int e0, T (&v)[8])
+template <typename T>
+__device__ __forceinline__ void adj_patch_hough(const AdjDesc& d, int s_row, int e0, T (&v)[8])
 {
-    const int W = d.W;
-    if constexpr (!FROM_HOUGH) {
-        const T* band = reinterpret_cast<const T*>(d.src) + (long long)s_row * d.src_ld;
+    const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int e = e0 + c;
-            if (e >= W) e -= W;
-            v[c] = (e < d.src_bw) ? band[e] : (T)0;
-        }
-    } else {
-        const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int e = e0 + c;
-            if (e >= W) e -= W;
-            v[c] = src[e];
-        }
-    }
+    for (int c = 0; c < 8; ++c) v[c] = src[run_col(e0, c, d.W, d.mirror)];
 }
 
 template <typename T>
@@ -738,69 +828,10 @@ __device__ __forceinline__ void acc_store8(T* p, const T (&v)[8], bool accumulat
     }
 }
 
-template <typename T, int GB, int DIR, bool FIRST, bool LAST>
-__device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* lds)
+template <typename T, int GB>
+__device__ __forceinline__ void adj_exchange(T (&b)[8][8], T (&a)[8][8], T* lds, int wave, int lane)
 {
-    constexpr int G = 3 + GB;
-    constexpr int NMINI = 1 << (6 - G);
-    constexpr int VW = kWinCols - (1 << G);
-    // transposed shifts point the other way, so the halo sits on the other side
-    constexpr int LOFF = DIR > 0 ? 0 : kLdsOffNeg;
-    const int lane = threadIdx.x & 63;
-    const int wave = uniform(threadIdx.x >> 6);
-    const int j0 = d.j0;
-    const int n_mini = d.n >> G;
-    const int x_lo = d.x_start + win * VW;
-    const int xw0 = x_lo - (DIR > 0 ? (1 << G) : 0);
-
-    // ---- load the forward pass's output rows (contiguous within a block)
-    T b[8][8];
-    {
-        int e0[8];
-        bool patch[8];
-        bool any = false;
-#pragma unroll
-        for (int rho = 0; rho < 8; ++rho) {
-            const int rp = rho & ((1 << GB) - 1);
-            const int q = rho >> GB;
-            const int kappa = (wave << (3 - GB)) + q;
-            const int t = kappa >> 3;
-            const int up = kappa & 7;
-            const int mu = rt * NMINI + t;
-            if (mu < n_mini) {
-                const int B = mu >> j0;
-                const int u = mu & ((1 << j0) - 1);
-                const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
-                patch[rho] = adj_issue_row<T, FIRST>(d, s_row, xw0, lane, b[rho], e0[rho]);
-            } else {
-                zero8(b[rho]);
-                patch[rho] = false;
-                e0[rho] = 0;
-            }
-            any |= patch[rho];
-        }
-        if (__any(any)) {
-#pragma unroll
-            for (int rho = 0; rho < 8; ++rho) {
-                if (patch[rho]) {
-                    const int rp = rho & ((1 << GB) - 1);
-                    const int q = rho >> GB;
-                    const int kappa = (wave << (3 - GB)) + q;
-                    const int t = kappa >> 3;
-                    const int up = kappa & 7;
-                    const int mu = rt * NMINI + t;
-                    const int B = mu >> j0;
-                    const int u = mu & ((1 << j0) - 1);
-                    const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
-                    adj_patch_row<T, FIRST>(d, s_row, e0[rho], b[rho]);
-                }
-            }
-        }
-    }
-    adj_stages_b<T, DIR, GB>(b);
-
-    // ---- exchange (two halves of LDS rows, as in the forward pass)
-    T a[8][8];
+    adj_stages_b<T, GB>(b);
     if constexpr (GB == 0) {
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -819,13 +850,12 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
                     const int t = kappa >> 3;
                     const int up = kappa & 7;
                     const int wa = (t << GB) + rp;
-                    const int off = uniform(DIR * up * rp + LOFF);
-                    lds_write8<T>(lds + (wa * 4 + (up & 3)) * kLdsRow + lane, off, b[rho]);
+                    lds_write8<T>(lds + (wa * 4 + (up & 3)) * kLdsRow + lane, uniform(up * rp), b[rho]);
                 }
             }
             __syncthreads();
             {
-                const T* lr = lds + wave * 4 * kLdsRow + lane + LOFF / 8;
+                const T* lr = lds + wave * 4 * kLdsRow + lane;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
@@ -834,38 +864,106 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
             if (h == 0) __syncthreads();
         }
     }
-    adj_stage<T, DIR, 2>(a);
-    adj_stage<T, DIR, 1>(a);
-    adj_stage<T, DIR, 0>(a);
+}
 
-    // ---- store row m of each mini transform at its offset dir*u*m
-    const int wc0 = 8 * lane;
-    const bool lane_ok = DIR > 0 ? (wc0 >= (1 << G)) : (wc0 < VW);
-    if (!lane_ok) return;
-    const int x0 = xw0 + wc0;  // window column of register 0 (before the offset)
+template <typename T, int GB, bool FIRST, bool LAST>
+__device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* lds)
+{
+    constexpr int G = 3 + GB;
+    constexpr int VW = kWinCols - (1 << G);
+    constexpr int nmini_tile = 1 << (6 - G);
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform(threadIdx.x >> 6);
+    const int j0 = d.j0;
+    const int n_mini = d.n >> G;
+    const int x_lo = d.x_start + win * VW;
+    const int xw0 = x_lo - (1 << G);             // xi of the tile's column 0 (halo first)
+    constexpr bool first = FIRST;                // reads the Hough gradient (else a band)
     const int W = d.W;
+
+    // ---- load the forward pass's output rows (contiguous within a block)
+    T b[8][8];
+    {
+        int e0[8];
+        bool patch[8];
+        bool any = false;
+        const T* band = reinterpret_cast<const T*>(d.src);
+#pragma unroll
+        for (int rho = 0; rho < 8; ++rho) {
+            const int rp = rho & ((1 << GB) - 1);
+            const int q = rho >> GB;
+            const int kappa = (wave << (3 - GB)) + q;
+            const int t = kappa >> 3;
+            const int up = kappa & 7;
+            const int mu = rt * nmini_tile + t;
+            patch[rho] = false;
+            e0[rho] = 0;
+            if (mu < n_mini) {
+                const int B = mu >> j0;
+                const int u = mu & ((1 << j0) - 1);
+                const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
+                if constexpr (first)
+                    patch[rho] = adj_issue_hough<T>(d, s_row, xw0, lane, b[rho], e0[rho]);
+                else
+                    patch[rho] = issue_band_row<T>(band + (long long)s_row * d.src_ld, d.src_off, d.src_bw, W, xw0,
+                                                   lane, b[rho], e0[rho]);
+            } else {
+                zero8(b[rho]);
+            }
+            any |= patch[rho];
+        }
+        if (__any(any)) {
+#pragma unroll
+            for (int rho = 0; rho < 8; ++rho) {
+                if (patch[rho]) {
+                    const int rp = rho & ((1 << GB) - 1);
+                    const int q = rho >> GB;
+                    const int kappa = (wave << (3 - GB)) + q;
+                    const int t = kappa >> 3;
+                    const int up = kappa & 7;
+                    const int mu = rt * nmini_tile + t;
+                    const int B = mu >> j0;
+                    const int u = mu & ((1 << j0) - 1);
+                    const int s_row = (B << (j0 + G)) + (u << G) + (up << GB) + rp;
+                    if constexpr (first) adj_patch_hough<T>(d, s_row, e0[rho], b[rho]);
+                    else patch_band_row<T>(band + (long long)s_row * d.src_ld, d.src_bw, W, e0[rho], b[rho]);
+                }
+            }
+        }
+    }
+
+    T a[8][8];
+    adj_exchange<T, GB>(b, a, lds, wave, lane);
+    adj_stage<T, 2>(a);
+    adj_stage<T, 1>(a);
+    adj_stage<T, 0>(a);
+
+    // ---- store row m of each mini transform at its offset u*m
+    const int wc0 = 8 * lane;
+    if (wc0 < (1 << G)) return;
+    const int xi = xw0 + wc0;  // xi of register 0 before the offset
     const int tr0 = wave * 8;
     const int t = tr0 >> G;
-    const int mu = rt * NMINI + t;
+    const int mu = rt * nmini_tile + t;
     if (mu >= n_mini) return;
     const int B = mu >> j0;
     const int u = mu & ((1 << j0) - 1);
     if constexpr (!LAST) {
         // band: window columns [0, W) are covered once; column z of row m lands
-        // on z + dir*u*m, a bijection of the cyclic row
-        if (x0 >= W) return;
+        // on z + u*m, a bijection of the cyclic row
+        if (xi >= W) return;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int m = (tr0 + r) & ((1 << G) - 1);
             const int R = (B << (j0 + G)) + (m << j0) + u;
             T* dst = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld;
-            const int e0 = wrap_lane(mod_w(xw0 + DIR * u * m + d.dst_off, W) + wc0, W);
-            if (x0 + 8 <= W && e0 + 8 <= d.dst_bw) {
+            const int e0 = wrap_up(mod_w(xw0 + u * m + d.dst_off, W) + wc0, W);
+            if (xi + 8 <= W && e0 + 8 <= d.dst_bw) {
                 store8<T>(dst + e0, a[r]);
             } else {
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    if (x0 + c < W) {
+                    if (xi + c < W) {
                         int e = e0 + c;
                         if (e >= W) e -= W;
                         if (e < d.dst_bw) dst[e] = a[r][c];
@@ -873,19 +971,33 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
                 }
             }
         }
-    } else if (d.dst_kind == 1) {
-        // image rows (the first forward pass has u = 0: no offset remains)
+        return;
+    }
+    // image (the first forward pass has u = 0: no offset remains); x = +-xi.
+    // The windows cover xi in [x_start, x_start + cols) once, which maps onto
+    // image columns 0..cols-1; anything past that is another window's.
+    const int cols = d.dst_kind == 1 ? d.img_w : d.img_h;
+    const int rel = xi - d.x_start;
+    if (rel >= cols) return;
+    const int e0 = d.mirror ? wrap_down(mod_w(-xi - 7, W), W) : wrap_up(mod_w(xi, W), W);
+    const bool full_run = rel + 8 <= cols && e0 + 8 <= cols;
+    if (d.dst_kind == 1) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int R = (B << G) + ((tr0 + r) & ((1 << G) - 1));
-            if (R >= d.img_h || x0 >= d.img_w) continue;
-            T* p = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x0;
-            if (x0 + 8 <= d.img_w) {
-                acc_store8<T>(p, a[r], d.accumulate != 0);
+            if (R >= d.img_h) continue;
+            T* p = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld;
+            if (full_run) {
+                T v[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v[c] = d.mirror ? a[r][7 - c] : a[r][c];
+                acc_store8<T>(p + e0, v, d.accumulate != 0);
             } else {
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (x0 + c < d.img_w) p[c] = d.accumulate ? (T)(p[c] + a[r][c]) : a[r][c];
+                for (int c = 0; c < 8; ++c) {
+                    const int e = run_col(e0, c, W, d.mirror);
+                    if (rel + c < cols && e < cols) p[e] = d.accumulate ? (T)(p[e] + a[r][c]) : a[r][c];
+                }
             }
         }
     } else {
@@ -894,8 +1006,8 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
         const bool all_cols = R0 + 8 <= d.img_w;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const int e = x0 + c;  // image row
-            if (e >= d.img_h) continue;
+            const int e = run_col(e0, c, W, d.mirror);  // image row
+            if (rel + c >= cols || e >= d.img_h) continue;
             T* p = reinterpret_cast<T*>(d.dst) + (long long)e * d.dst_ld + R0;
             T v[8];
 #pragma unroll
@@ -917,19 +1029,62 @@ __global__ __launch_bounds__(kThreads, 4) void fht_adj_pass_kernel(const AdjLaun
     __shared__ T lds[kTileRows / 2 * kLdsRow];
     const AdjDesc& d = L.d[blockIdx.z];
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
-    if (d.dir > 0) adj_tile<T, GB, 1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
-    else adj_tile<T, GB, -1, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
+    adj_tile<T, GB, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
 }
 
-// Adjoint for n <= 4 rows: B_j from B_{j+1} by the transposed stage, top-down.
+// -------------------------------------------- direct form for n <= 4 rows
+
+template <typename TIn, typename T>
+__device__ __forceinline__ T src_value(const PassDesc& d, int R, int x)
+{
+    const int W = d.W;
+    const int e = mod_pos((long long)x - shear_of_row(R, d.S1, d.n), W);
+    const TIn* img = reinterpret_cast<const TIn*>(d.src);
+    if (d.src_kind == SRC_IMAGE)
+        return (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + e]) : (T)0;
+    return (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)e * d.src_ld + R]) : (T)0;
+}
+
+// The same add tree as K stages of the recurrence, evaluated top-down in x
+// (direction -1 for mirrored quadrants).
+template <typename TIn, typename T, int K>
+__device__ T direct_sum(const PassDesc& d, int base, int s, int x)
+{
+    if constexpr (K == 0) {
+        return src_value<TIn, T>(d, base, x);
+    } else {
+        const int sub = s >> 1;
+        const int dir = d.mirror ? -1 : 1;
+        const T top = direct_sum<TIn, T, K - 1>(d, base, sub, x);
+        const T bot = direct_sum<TIn, T, K - 1>(d, base + (1 << (K - 1)), sub,
+                                               mod_pos((long long)x + dir * (s - sub), d.W));
+        return top + bot;
+    }
+}
+
+template <typename TIn, typename T, int K>
+__global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
+{
+    const PassDesc& d = L.d[blockIdx.z];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (x >= d.W || s >= d.n || s > d.row_limit || s == d.skip_row) return;
+    const T v = direct_sum<TIn, T, K>(d, 0, s, x);
+    T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
+    const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
+    dst[mod_pos((long long)x + roll, d.W)] = v;
+}
+
+// Adjoint for n <= 4 rows: B_j from B_{j+1} by the transposed stage, top-down
+// in x.
 template <typename T, int J, int K>
 __device__ T adj_direct(const AdjDesc& d, int row, int x)
 {
     if constexpr (J == K) {
-        T v[8];
-        int e0;
-        if (adj_issue_row<T, true>(d, row, x, 0, v, e0)) adj_patch_row<T, true>(d, row, e0, v);
-        return v[0];  // only the first column is used
+        if (row == d.skip_row) return (T)0;
+        const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * row) * d.src_ld;
+        const int roll = d.shifted ? ((d.roll_a + d.roll_b * row) >> 1) : 0;
+        return src[mod_pos((long long)x + roll, d.W)];
     } else {
         const int blk = 1 << J;
         const int base = (row / (2 * blk)) * (2 * blk);
@@ -938,8 +1093,9 @@ __device__ T adj_direct(const AdjDesc& d, int row, int x)
             return adj_direct<T, J + 1, K>(d, base + 2 * i, x) + adj_direct<T, J + 1, K>(d, base + 2 * i + 1, x);
         }
         const int u = i - blk;
-        return adj_direct<T, J + 1, K>(d, base + 2 * u, mod_pos((long long)x - d.dir * u, d.W)) +
-               adj_direct<T, J + 1, K>(d, base + 2 * u + 1, mod_pos((long long)x - d.dir * (u + 1), d.W));
+        const int dir = d.mirror ? -1 : 1;
+        return adj_direct<T, J + 1, K>(d, base + 2 * u, mod_pos((long long)x - dir * u, d.W)) +
+               adj_direct<T, J + 1, K>(d, base + 2 * u + 1, mod_pos((long long)x - dir * (u + 1), d.W));
     }
 }
 

@@ -1,5 +1,5 @@
-// Launch templates of the pass kernels; each element type is instantiated in
-// its own translation unit (fht_fwd_*.hip, fht_adj_*.hip) so they compile in
+// Launch templates of the kernels; each element type is instantiated in its
+// own translation unit (fht_fwd_*.hip, fht_adj_*.hip) so they compile in
 // parallel.
 #pragma once
 
@@ -7,39 +7,82 @@
 
 namespace fht {
 
-inline dim3 pass_grid(const PassLaunch& L)
+template <typename TIn, typename T, int GB>
+hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
 {
-    int wx = 1, ry = 1;
-    for (int i = 0; i < L.nd; ++i) {
-        wx = L.d[i].n_windows > wx ? L.d[i].n_windows : wx;
-        ry = L.d[i].n_row_tiles > ry ? L.d[i].n_row_tiles : ry;
-    }
-    return dim3(wx, ry, L.nd);
-}
-
-template <typename TIn, typename T, bool FIRST, bool LAST>
-hipError_t launch_pass_fl(const PassLaunch& L, int G, hipStream_t s)
-{
-    const dim3 grid = pass_grid(L);
-    switch (G) {
-    case 3: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 0, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    case 4: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 1, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    case 5: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 2, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    case 6: hipLaunchKernelGGL((fht_pass_kernel<TIn, T, 3, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    default: return hipErrorInvalidValue;
-    }
+    PassLaunch L = L0;
+    L.n_tiles = 0;
+    for (int i = 0; i < L.nd; ++i) L.n_tiles += L.d[i].n_row_tiles * L.d[i].n_windows;
+    if (L.n_tiles == 0) return hipSuccess;
+    const bool first = L.d[0].src_kind != SRC_BAND, last = L.d[0].dst_kind == DST_HOUGH;
+    const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds);
+    if (first && last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true>), grid, dim3(kThreads), 0, s, L);
+    else if (first) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false>), grid, dim3(kThreads), 0, s, L);
+    else if (last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true>), grid, dim3(kThreads), 0, s, L);
+    else hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false>), grid, dim3(kThreads), 0, s, L);
     return hipGetLastError();
 }
 
-// first = the pass reads the image, last = the pass writes the Hough image
+// all descriptors of one launch share G and first/last
 template <typename TIn, typename T>
-hipError_t launch_pass_t(const PassLaunch& L, int G, bool first, bool last, hipStream_t s)
+hipError_t launch_pass_t(const PassLaunch& L, hipStream_t s)
 {
-    if (first) return last ? launch_pass_fl<TIn, T, true, true>(L, G, s) : launch_pass_fl<TIn, T, true, false>(L, G, s);
-    if constexpr (sizeof(TIn) == sizeof(T)) {
-        return last ? launch_pass_fl<T, T, false, true>(L, G, s) : launch_pass_fl<T, T, false, false>(L, G, s);
+    switch (L.d[0].G) {
+    case 3: return launch_pass_g<TIn, T, 0>(L, s);
+    case 4: return launch_pass_g<TIn, T, 1>(L, s);
+    case 5: return launch_pass_g<TIn, T, 2>(L, s);
+    case 6: return launch_pass_g<TIn, T, 3>(L, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
+}
+
+template <typename TIn, typename T, int GB>
+hipError_t launch_engine_g(const EngineArgs& A, int grid, hipStream_t s)
+{
+    if (A.table) hipLaunchKernelGGL((fht_engine_kernel<TIn, T, GB, false>), dim3(grid), dim3(kThreads), 0, s, A);
+    else hipLaunchKernelGGL((fht_engine_kernel<TIn, T, GB, true>), dim3(grid), dim3(kThreads), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename TIn, typename T, int GB>
+hipError_t launch_table_g(const EngineGroup* table, int n_groups, int n_items, bool first, bool last, hipStream_t s)
+{
+    const dim3 grid((n_items + kXcds - 1) / kXcds * kXcds);
+    if (first && last)
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, true>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+    else if (first)
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, false>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+    else if (last)
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, true>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+    else
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, false>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+    return hipGetLastError();
+}
+
+template <typename TIn, typename T>
+hipError_t launch_table_t(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last,
+                          hipStream_t s)
+{
+    switch (G) {
+    case 3: return launch_table_g<TIn, T, 0>(table, n_groups, n_items, first, last, s);
+    case 4: return launch_table_g<TIn, T, 1>(table, n_groups, n_items, first, last, s);
+    case 5: return launch_table_g<TIn, T, 2>(table, n_groups, n_items, first, last, s);
+    case 6: return launch_table_g<TIn, T, 3>(table, n_groups, n_items, first, last, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// every group of one engine launch has G = 3 + GB
+template <typename TIn, typename T>
+hipError_t launch_engine_t(const EngineArgs& A, int G, int grid, hipStream_t s)
+{
+    switch (G) {
+    case 3: return launch_engine_g<TIn, T, 0>(A, grid, s);
+    case 4: return launch_engine_g<TIn, T, 1>(A, grid, s);
+    case 5: return launch_engine_g<TIn, T, 2>(A, grid, s);
+    case 6: return launch_engine_g<TIn, T, 3>(A, grid, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename TIn, typename T>
@@ -60,31 +103,34 @@ hipError_t launch_direct_t(const PassLaunch& L, int k, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, bool FIRST, bool LAST>
-hipError_t launch_adj_pass_fl(const AdjLaunch& L, int G, hipStream_t s)
+template <typename T, int GB>
+hipError_t launch_adj_pass_g(const AdjLaunch& L, hipStream_t s)
 {
     int wx = 1, ry = 1;
     for (int i = 0; i < L.nd; ++i) {
         wx = L.d[i].n_windows > wx ? L.d[i].n_windows : wx;
         ry = L.d[i].n_row_tiles > ry ? L.d[i].n_row_tiles : ry;
     }
+    const bool first = L.d[0].src_kind == 0, last = L.d[0].dst_kind != 0;
     const dim3 grid(wx, ry, L.nd);
-    switch (G) {
-    case 3: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 0, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    case 4: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 1, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    case 5: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 2, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    case 6: hipLaunchKernelGGL((fht_adj_pass_kernel<T, 3, FIRST, LAST>), grid, dim3(kThreads), 0, s, L); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (first && last) hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, true>), grid, dim3(kThreads), 0, s, L);
+    else if (first) hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, false>), grid, dim3(kThreads), 0, s, L);
+    else if (last) hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, true>), grid, dim3(kThreads), 0, s, L);
+    else hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, false>), grid, dim3(kThreads), 0, s, L);
     return hipGetLastError();
 }
 
-// first = reads the Hough gradient, last = writes the image gradient
+// all descriptors of one launch share G and first/last
 template <typename T>
-hipError_t launch_adj_pass_t(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s)
+hipError_t launch_adj_pass_t(const AdjLaunch& L, hipStream_t s)
 {
-    if (first) return last ? launch_adj_pass_fl<T, true, true>(L, G, s) : launch_adj_pass_fl<T, true, false>(L, G, s);
-    return last ? launch_adj_pass_fl<T, false, true>(L, G, s) : launch_adj_pass_fl<T, false, false>(L, G, s);
+    switch (L.d[0].G) {
+    case 3: return launch_adj_pass_g<T, 0>(L, s);
+    case 4: return launch_adj_pass_g<T, 1>(L, s);
+    case 5: return launch_adj_pass_g<T, 2>(L, s);
+    case 6: return launch_adj_pass_g<T, 3>(L, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -107,14 +153,18 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
 }
 
 // per-type entry points (defined in the instantiation units)
-hipError_t launch_pass_u8(const PassLaunch& L, int G, bool first, bool last, hipStream_t s);
-hipError_t launch_pass_i32(const PassLaunch& L, int G, bool first, bool last, hipStream_t s);
-hipError_t launch_pass_f32(const PassLaunch& L, int G, bool first, bool last, hipStream_t s);
-hipError_t launch_direct_u8(const PassLaunch& L, int k, hipStream_t s);
-hipError_t launch_direct_i32(const PassLaunch& L, int k, hipStream_t s);
-hipError_t launch_direct_f32(const PassLaunch& L, int k, hipStream_t s);
-hipError_t launch_adj_pass_i32(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s);
-hipError_t launch_adj_pass_f32(const AdjLaunch& L, int G, bool first, bool last, hipStream_t s);
+#define FHT_DECLARE_FWD(name)                                                   \
+    hipError_t launch_pass_##name(const PassLaunch& L, hipStream_t s);           \
+    hipError_t launch_engine_##name(const EngineArgs& A, int G, int grid, hipStream_t s); \
+    hipError_t launch_direct_##name(const PassLaunch& L, int k, hipStream_t s);                 \
+    hipError_t launch_table_##name(const EngineGroup* table, int n_groups, int n_items, int G, bool first, \
+                                   bool last, hipStream_t s);
+FHT_DECLARE_FWD(u8)
+FHT_DECLARE_FWD(i32)
+FHT_DECLARE_FWD(f32)
+#undef FHT_DECLARE_FWD
+hipError_t launch_adj_pass_i32(const AdjLaunch& L, hipStream_t s);
+hipError_t launch_adj_pass_f32(const AdjLaunch& L, hipStream_t s);
 hipError_t launch_adj_direct_i32(const AdjLaunch& L, int k, hipStream_t s);
 hipError_t launch_adj_direct_f32(const AdjLaunch& L, int k, hipStream_t s);
 

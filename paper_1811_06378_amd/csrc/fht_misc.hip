@@ -15,11 +15,28 @@ __global__ void fht_zero_kernel(uint32_t* p, int64_t rows, int64_t cols_words, i
 }
 
 // dtype codes: 0 = u8, 1 = i32, 2 = f32
-hipError_t launch_pass(const PassLaunch& L, int G, bool first, bool last, int in_t, int acc_t, hipStream_t s)
+hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s)
 {
-    if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, G, first, last, s);
-    if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, G, first, last, s);
-    if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, G, first, last, s);
+    if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, s);
+    if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, s);
+    if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc_t, hipStream_t s)
+{
+    if (in_t == 0 && acc_t == 1) return launch_engine_u8(A, G, grid, s);
+    if (in_t == 1 && acc_t == 1) return launch_engine_i32(A, G, grid, s);
+    if (in_t == 2 && acc_t == 2) return launch_engine_f32(A, G, grid, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int in_t,
+                        int acc_t, hipStream_t s)
+{
+    if (in_t == 0 && acc_t == 1) return launch_table_u8(table, n_groups, n_items, G, first, last, s);
+    if (in_t == 1 && acc_t == 1) return launch_table_i32(table, n_groups, n_items, G, first, last, s);
+    if (in_t == 2 && acc_t == 2) return launch_table_f32(table, n_groups, n_items, G, first, last, s);
     return hipErrorInvalidValue;
 }
 
@@ -31,10 +48,10 @@ hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStr
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_adjoint_pass(const AdjLaunch& L, int G, bool first, bool last, int t, hipStream_t s)
+hipError_t launch_adjoint_pass(const AdjLaunch& L, int t, hipStream_t s)
 {
-    if (t == 1) return launch_adj_pass_i32(L, G, first, last, s);
-    if (t == 2) return launch_adj_pass_f32(L, G, first, last, s);
+    if (t == 1) return launch_adj_pass_i32(L, s);
+    if (t == 2) return launch_adj_pass_f32(L, s);
     return hipErrorInvalidValue;
 }
 
@@ -43,6 +60,17 @@ hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s
     if (t == 1) return launch_adj_direct_i32(L, k, s);
     if (t == 2) return launch_adj_direct_f32(L, k, s);
     return hipErrorInvalidValue;
+}
+
+// Persistent grid: two 512-thread workgroups per CU (LDS and registers both
+// allow two), on the current device.
+int engine_grid_size()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 512;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 512;
+    return 2 * cus;
 }
 
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s)

@@ -347,6 +347,19 @@ class BatchPlan:
         self.run(self.pointer_table(imgs), packed)
         return self.views(packed)
 
+    def capture(self, ptr_table: torch.Tensor, packed: torch.Tensor):
+        """Capture one batched forward into a HIP graph (torch.cuda.CUDAGraph);
+        replaying it reruns the whole batch with the same buffers."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run(ptr_table, packed)  # warm-up outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(g):
+            self.run(ptr_table, packed)
+        return g
+
     def __del__(self):
         p = getattr(self, "_plan", None)
         if p is not None and p.value and _lib is not None:

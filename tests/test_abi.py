@@ -74,7 +74,8 @@ def test_workspace_size_monotone():
     a = fht.workspace_size(1024, 1024)
     b = fht.workspace_size(4096, 4096)
     assert 0 < a < b
-    assert fht.workspace_size(64, 64) == 0          # one pass: no intermediate band
+    # one pass: no intermediate band, only the 256-byte queue/counter area
+    assert fht.workspace_size(64, 64) == 256
 
 
 def test_validation_before_hip():
@@ -125,3 +126,17 @@ def test_product_path_has_no_oracle_import():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "fht_oracle" not in text, f
+
+
+def test_batch_plan_host_side():
+    """Plan arguments are validated before any HIP call."""
+    L = fht.lib()
+    p = ctypes.c_void_p()
+    wsb, tot = ctypes.c_size_t(), ctypes.c_int64()
+    ws = (ctypes.c_int32 * 2)(3, 8)
+    hs = (ctypes.c_int32 * 2)(8, 8)
+    assert L.fht_batch_plan_create(ws, hs, 2, 15, 0, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
+                                   None) == fht.FHT_ERR_UNSUPPORTED
+    assert L.fht_batch_plan_create(ws, hs, 2, 15, 2, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
+                                   None) == fht.FHT_ERR_INVALID
+    assert L.fht_batch_plan_destroy(None) == 0
