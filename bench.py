@@ -4,15 +4,23 @@
 One step = one full forward transform (all four quadrants, merged full Hough
 image of 16381 x 8192 float32) of a synthetic, seeded image already resident
 in HBM.  Prints one JSON line:
-  value        input Gpixels/s of the forward (4096^2 pixels per step)
-  fwd_adjoint  Gpixels/s of forward + adjoint (the backward of the transform)
-  batched      Gpixels/s of the batched forward over 8 such images
-  roofline     the dominant kernel against the 8 TB/s HBM roof
-  cpu_baseline the CPU oracle on this host's cores (bounded sample)
+  value         input Gpixels/s of the forward (4096^2 pixels per step)
+  roofline      the dominant kernel (last pass) against the 8 TB/s HBM roof:
+                its algorithmic bytes per launch over its average launch time,
+                measured with HIP events on its launch stream in the timed
+                region; traffic = HBM bytes per launch from the committed
+                counter summary (null when the kernel sources have changed)
+  fwd_adjoint   forward + adjoint (the backward of the transform)
+  batched       8 such images through one batch plan (HIP graph replay),
+                beside a loop of 8 single-image forwards
+  batch512      512 uint8 images with sides uniform in 64..2048 (graph
+                replay), beside a loop of 512 single-image forwards
+  cpu_baseline  the CPU oracle on this host's cores (bounded sample)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +30,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+CSRC = os.path.join(ROOT, "paper_1811_06378_amd", "csrc")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fht_pass_kernel_last_dense4096_traffic.txt")
+
+
+def sources_digest() -> str:
+    """sha256 over the kernel sources (name + bytes, sorted)."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if absent, for another kernel, or taken on other sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def _timed(fn, steps, warmup, torch):
@@ -30,14 +68,26 @@ def _timed(fn, steps, warmup, torch):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
     e0.record()
     for _ in range(steps):
         fn()
     e1.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall
+    return e0.elapsed_time(e1) / steps
+
+
+def last_pass_algorithmic_bytes(fht, w: int, h: int, elem: int) -> int:
+    """Bytes the last pass of a two-pass full transform must move: read every
+    quadrant's first-pass band (n rows of other + 2^G1 - 1 columns, where G1
+    is the first pass's stage count) and write the full Hough image once."""
+    wp, hp = 1 << max(0, (w - 1).bit_length()), 1 << max(0, (h - 1).bit_length())
+    total = 0
+    for n, other in ((hp, wp), (hp, wp), (wp, hp), (wp, hp)):
+        split = fht.pass_split(n)
+        assert len(split) == 2, "the roofline formula covers two-pass sizes"
+        total += n * (other + (1 << split[0]) - 1) * elem
+    rows, cols = fht.hough_shape(w, h)
+    return total + rows * cols * elem
 
 
 def cpu_baseline(img, target_s: float = 10.0):
@@ -58,6 +108,42 @@ def cpu_baseline(img, target_s: float = 10.0):
             "sample": "%d full float64 transform(s) of the same 4096x4096 image, %.1f s" % (reps, total)}
 
 
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def bench_batch(fht, torch, imgs, steps, warmup, label):
+    """Batched forward (captured once in a HIP graph, replayed) and the same
+    images through single-image forwards, into the same packed output."""
+    sizes = [tuple(x.shape) for x in imgs]
+    plan = fht.BatchPlan(sizes, in_dtype=imgs[0].dtype)
+    table = plan.pointer_table(imgs)
+    packed = plan.output()
+    graph = plan.capture(table, packed)
+    ms_batch = _timed(graph.replay, steps, warmup, torch)
+    views = plan.views(packed)
+    ws = torch.empty(max(max(fht.workspace_size(w, h, "full", imgs[0].dtype) for h, w in sizes), 256),
+                     dtype=torch.uint8, device="cuda")
+
+    def loop():
+        for x, v in zip(imgs, views):
+            fht.forward(x, out=v, workspace=ws)
+
+    ms_loop = _timed(loop, steps, warmup, torch)
+    px = sum(h * w for h, w in sizes)
+    out_bytes = plan.out_elems * 4
+    in_bytes = sum(x.numel() * x.element_size() for x in imgs)
+    res = {"value": round(px / (ms_batch * 1e-3) / 1e9, 3), "unit": "Gpixels/s", "ms_per_step": round(ms_batch, 4),
+           "images": len(imgs), "pixels": px, "hough_cells": plan.out_elems,
+           "hbm_compulsory_frac": round((in_bytes + out_bytes) / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "single_image_loop": {"value": round(px / (ms_loop * 1e-3) / 1e9, 3), "ms_per_step": round(ms_loop, 4)},
+           "launch": "one batch plan, captured in a HIP graph and replayed"}
+    log("%s: batched %.3f ms, single-image loop %.3f ms" % (label, ms_batch, ms_loop))
+    del graph, packed, views, plan
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,10 +156,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the transform shards "
-              "by image, quadrant or column band; see DESIGN.md).", file=sys.stderr)
+              "by image, quadrant or column band without a collective on the hot path).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1811_06378_amd import fht, synth
@@ -95,15 +180,32 @@ def main():
     out = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
     ws = torch.empty(max(fht.workspace_size(side, side, "full", torch.float32), 256), dtype=torch.uint8,
                      device="cuda")
-    print("bench: forward %dx%d float32 -> %dx%d, %d steps after %d warmup" % (side, side, rows, cols, args.steps,
-                                                                             args.warmup), file=sys.stderr, flush=True)
+    log("forward %dx%d float32 -> %dx%d, %d steps after %d warmup" % (side, side, rows, cols, args.steps,
+                                                                   args.warmup))
 
-    ms_fwd, wall_fwd = _timed(lambda: fht.forward(x, out=out, workspace=ws), args.steps, args.warmup, torch)
+    def step():
+        fht.forward(x, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # timed region: every pass launch bracketed by HIP events on its stream
+    fht.timing_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    fht.timing_enable(False)
+    ms_fwd = e0.elapsed_time(e1) / args.steps
+    kernels = fht.timing_report()
     px = side * side
     value = px / (ms_fwd * 1e-3) / 1e9
 
     result = {
-        "metric": "Gpixels/s full 4-quadrant FHT 4096^2 (fwd, fwd+adjoint, batched); % HBM peak",
+        "metric": "Gpixels/s full 4-quadrant FHT 4096² (fwd, fwd+adjoint, batched); % HBM peak",
         "value": round(value, 3),
         "unit": "Gpixels/s",
         "n_gpus": 1,
@@ -114,37 +216,61 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Exp(1) image with 16 planted lines)",
-        "config": {"workload": "dense4096", "image": [side, side], "hough": [rows, cols], "quads": "full",
-                   "fhtshift": False, "parallelism": "single GPU"},
+        "data": "synthetic (seeded Exp(1) 4096x4096 image with 16 planted lines of +20)",
+        "config": {"workload": "dense4096: 4096x4096 float32, full four-quadrant Hough image 16381x8192 float32",
+                   "image": [side, side], "hough": [rows, cols], "quads": "full", "fhtshift": False},
     }
 
-    # compulsory traffic of one forward: read the image once, write the Hough image once
-    in_bytes = px * 4
-    out_bytes = rows * cols * 4
-    compulsory = in_bytes + out_bytes
+    # whole-transform compulsory traffic: read the image once, write the Hough image once
+    compulsory = px * 4 + rows * cols * 4
     result["hbm_compulsory_frac"] = round(compulsory / (ms_fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    # dominant kernel: the largest summed launch time in the timed region
+    name, (launches, total_ms) = max(kernels.items(), key=lambda kv: kv[1][1])
+    avg_ms = total_ms / launches
+    alg = last_pass_algorithmic_bytes(fht, side, side, 4)
+    if "fht_pass_kernel<float, float, 3, false, true>" not in name:
+        alg = None  # the byte formula below is that kernel's
+    achieved = alg / (avg_ms * 1e-3) / 1e9 if alg else None
     result["roofline"] = {
         "bound": "hbm",
-        "achieved": round(compulsory / (ms_fwd * 1e-3) / 1e9, 1),
+        "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(compulsory / (ms_fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "kernel": "forward (all launches of one step)",
-        "algorithmic_bytes": compulsory,
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": committed_traffic(name),
+        "kernel": name,
+        "launch_ms": round(avg_ms, 4),
+        "launches": launches,
+        "algorithmic_bytes_per_launch": alg,
+        "kernel_times_ms": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
     }
 
     if not args.fwd_only:
         g = torch.empty_like(out).normal_()
         gimg = torch.empty_like(x)
-        ms_fa, _ = _timed(lambda: (fht.forward(x, out=out, workspace=ws), fht.adjoint(g, side, side, out=gimg)),
-                          max(1, args.steps // 2), 1, torch)
+        ms_fa = _timed(lambda: (fht.forward(x, out=out, workspace=ws), fht.adjoint(g, side, side, out=gimg)),
+                       max(1, args.steps // 2), 1, torch)
         result["fwd_adjoint"] = {"value": round(px / (ms_fa * 1e-3) / 1e9, 3), "unit": "Gpixels/s",
-                                 "ms_per_step": round(ms_fa, 4)}
+                                 "ms_per_step": round(ms_fa, 4),
+                                 "hbm_compulsory_frac": round(2 * compulsory / (ms_fa * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                              4)}
+        del g, gimg
+        log("fwd+adjoint %.3f ms" % ms_fa)
+
+        imgs8 = [x] + [torch.from_numpy(synth.dense4096(s, size=side)).cuda() for s in range(1, 8)]
+        result["batched"] = bench_batch(fht, torch, imgs8, max(1, args.steps // 4), 1, "batched 8x4096^2 f32")
+        result["batched"]["workload"] = "8 dense4096 images (seeds 0..7), float32"
+        del imgs8
+
+        imgs512 = [torch.from_numpy(a).cuda() for a in synth.batch512(0)]
+        result["batch512"] = bench_batch(fht, torch, imgs512, 3, 1, "batch512 u8")
+        result["batch512"]["workload"] = "512 uint8 images, sides uniform in 64..2048 (seed 0), int32 Hough images"
+        del imgs512
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        log("CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(img_np)
 
     print(json.dumps(result))

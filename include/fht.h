@@ -161,21 +161,29 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 void* stream);
 
 /*
- * Batched forward over many images of different sizes, executed by one
- * persistent kernel launch (ordered work queue with per-pass dependency
- * counters) that fht_batch_forward enqueues on the stream; the launch can be
- * captured in a hipGraph once the plan exists.  Each image is transformed as
- * by fht_forward(quads, flags = 0) into its own slice of one packed output
- * buffer.
+ * Batched forward over many images of different sizes (many independent
+ * transforms of sections 3.1 and 3.3).  Each image is transformed as by
+ * fht_forward(quads, flags = 0) into its own slice of one packed output
+ * buffer.  The plan fixes, once, every pass of every quadrant of every image;
+ * a call enqueues one small table-resolving kernel and then one launch per
+ * (pass, stages, last-pass) class covering every tile of every image in that
+ * class.  All work is kernel launches on the caller's stream, so a call can
+ * be captured in a hipGraph and replayed.  Images are processed in chunks
+ * whose intermediate bands fit 8 GiB, which bounds the workspace.
  *
- * fht_batch_plan_create: ws[i], hs[i] are the n image sizes (host arrays).
- *   Allocates the plan's device tables (the only allocating entry point).
- *   *ws_bytes receives the workspace size, *out_elems the total number of
- *   output elements; out_offsets (host, n entries, may be NULL) receives each
- *   image's element offset in the packed output (each image's Hough image is
- *   stored densely, ld_hough = W_i).
+ * fht_batch_plan_create: ws[i], hs[i] are the n image sizes (host arrays),
+ *   every side >= 5 (FHT_ERR_UNSUPPORTED otherwise; transform such tiny
+ *   images with fht_forward).  Allocates the plan's device tables (the only
+ *   allocating entry point) on the current device.  *ws_bytes receives the
+ *   workspace size, *out_elems the total number of output elements;
+ *   out_offsets (host, n entries, may be NULL) receives each image's element
+ *   offset in the packed output (each image's Hough image is stored densely,
+ *   ld_hough = W_i).
  * fht_batch_forward: imgs is a DEVICE array of n device pointers (image i
- *   dense, ld = w_i); hough is the packed output.
+ *   dense, ld = w_i); hough is the packed output; workspace is 256-byte
+ *   aligned, at least *ws_bytes.  A plan is immutable: concurrent calls on
+ *   different streams need their own workspace.
+ * fht_batch_plan_destroy: frees the plan's tables (NULL is a no-op).
  */
 typedef struct fht_batch_plan fht_batch_plan;
 int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned quads, int in_t,
@@ -184,6 +192,22 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
 int fht_batch_forward(const fht_batch_plan* plan, const void* const* imgs, void* hough,
                       void* workspace, size_t ws_bytes, void* stream);
 int fht_batch_plan_destroy(fht_batch_plan* plan);
+
+/*
+ * Launch timing (instrumentation, not part of the method).  fht_timing_enable
+ * (1) clears previous records and starts recording: every pass kernel the
+ * library enqueues afterwards (forward, range, adjoint and batched passes) is
+ * bracketed by two HIP events on its launch stream; launches inside a stream
+ * capture are not recorded.  fht_timing_enable(0) stops recording.
+ * fht_timing_report(index, ...) waits for the recorded events and returns,
+ * for the index-th kernel instantiation seen (in first-launch order), its
+ * name as "fht::<kernel><template arguments>" (copied into name, at most
+ * name_cap bytes with the terminator), the number of launches and their
+ * summed elapsed time in milliseconds; FHT_ERR_INVALID past the last one.
+ * The device is the one current at fht_timing_enable(1).
+ */
+int fht_timing_enable(int on);
+int fht_timing_report(int index, char* name, int name_cap, int64_t* launches, double* total_ms);
 
 /* Stage-fusion split chosen for a side (number of passes and stages per pass),
  * for inspection and tests.  passes[] receives up to 4 entries. */

@@ -21,7 +21,7 @@
 
 namespace fht {
 
-constexpr size_t kBatchBandBudget = size_t(2) << 30;  // bytes of bands per chunk
+constexpr size_t kBatchBandBudget = size_t(8) << 30;  // bytes of bands per chunk
 
 struct BatchLaunch {
     int first_group;  // index into the table

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace fht {
 
 // Tile geometry of the fused pass kernel.  One workgroup holds 64 rows x 512
@@ -123,5 +125,13 @@ hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,
                         int hp, int wp, int inverse, hipStream_t s);
 int engine_grid_size();
+
+// Launch timing (fht_timing_enable): the rocprof-style name of a pass kernel
+// instantiation (in_t < 0: adjoint kernels, one type), and the event pair
+// around one launch.  timing_begin returns -1 when timing is off.
+std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last);
+bool timing_on();
+int timing_begin(const std::string& name, hipStream_t s);
+void timing_end(int slot, hipStream_t s);
 
 }  // namespace fht

@@ -15,12 +15,23 @@ __global__ void fht_zero_kernel(uint32_t* p, int64_t rows, int64_t cols_words, i
 }
 
 // dtype codes: 0 = u8, 1 = i32, 2 = f32
-hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s)
+static hipError_t launch_pass_typed(const PassLaunch& L, int in_t, int acc_t, hipStream_t s)
 {
     if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, s);
     if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, s);
     if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s)
+{
+    int slot = -1;
+    if (timing_on())
+        slot = timing_begin(kernel_name("fht_pass_kernel", in_t, acc_t, L.d[0].G - 3, L.d[0].src_kind != SRC_BAND,
+                                        L.d[0].dst_kind == DST_HOUGH), s);
+    const hipError_t e = launch_pass_typed(L, in_t, acc_t, s);
+    timing_end(slot, s);
+    return e;
 }
 
 hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc_t, hipStream_t s)
@@ -31,13 +42,23 @@ hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int in_t,
-                        int acc_t, hipStream_t s)
+static hipError_t launch_table_typed(const EngineGroup* table, int n_groups, int n_items, int G, bool first,
+                                     bool last, int in_t, int acc_t, hipStream_t s)
 {
     if (in_t == 0 && acc_t == 1) return launch_table_u8(table, n_groups, n_items, G, first, last, s);
     if (in_t == 1 && acc_t == 1) return launch_table_i32(table, n_groups, n_items, G, first, last, s);
     if (in_t == 2 && acc_t == 2) return launch_table_f32(table, n_groups, n_items, G, first, last, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int in_t,
+                        int acc_t, hipStream_t s)
+{
+    int slot = -1;
+    if (timing_on()) slot = timing_begin(kernel_name("fht_table_kernel", in_t, acc_t, G - 3, first, last), s);
+    const hipError_t e = launch_table_typed(table, n_groups, n_items, G, first, last, in_t, acc_t, s);
+    timing_end(slot, s);
+    return e;
 }
 
 hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s)
@@ -50,9 +71,15 @@ hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStr
 
 hipError_t launch_adjoint_pass(const AdjLaunch& L, int t, hipStream_t s)
 {
-    if (t == 1) return launch_adj_pass_i32(L, s);
-    if (t == 2) return launch_adj_pass_f32(L, s);
-    return hipErrorInvalidValue;
+    int slot = -1;
+    if (timing_on())
+        slot = timing_begin(kernel_name("fht_adj_pass_kernel", -1, t, L.d[0].G - 3, L.d[0].src_kind == 0,
+                                        L.d[0].dst_kind != 0), s);
+    hipError_t e = hipErrorInvalidValue;
+    if (t == 1) e = launch_adj_pass_i32(L, s);
+    if (t == 2) e = launch_adj_pass_f32(L, s);
+    timing_end(slot, s);
+    return e;
 }
 
 hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s)

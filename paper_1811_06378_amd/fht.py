@@ -10,7 +10,8 @@ Names follow the C ABI in include/fht.h:
   shift(hough, w, h, inverse)                 section 5 (fhtshift)
   adjoint(grad, w, h, quads, shifted)         transpose of forward
   FHTFunction                                 autograd wrapper
-  BatchPlan                                   batched forward (one persistent launch)
+  BatchPlan                                   batched forward (graph-capturable)
+  timing_enable / timing_report               per-kernel launch times (HIP events)
 """
 from __future__ import annotations
 
@@ -59,6 +60,8 @@ SIGNATURES = {
     "fht_batch_forward": (_I, [_P, _P, _P, _P, _SZ, _P]),
     "fht_batch_plan_destroy": (_I, [_P]),
     "fht_pass_split": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "fht_timing_enable": (_I, [_I]),
+    "fht_timing_report": (_I, [_I, ctypes.c_char_p, _I, _PI64, ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -296,8 +299,33 @@ def fht(img, quads="full", shifted=False):
     return FHTFunction.apply(img, quads, shifted)
 
 
+def timing_enable(on: bool = True):
+    """Start (clearing earlier records) or stop recording HIP events around
+    every pass kernel launch of the library."""
+    _check(lib().fht_timing_enable(int(on)), "fht_timing_enable")
+
+
+def timing_report():
+    """{kernel name: (launches, total ms)} of the launches recorded since
+    timing_enable(True); waits for the recorded events."""
+    L = lib()
+    out = {}
+    i = 0
+    buf = ctypes.create_string_buffer(256)
+    while True:
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        rc = L.fht_timing_report(i, buf, 256, ctypes.byref(n), ctypes.byref(ms))
+        if rc == FHT_ERR_INVALID:
+            break
+        _check(rc, "fht_timing_report")
+        out[buf.value.decode()] = (n.value, ms.value)
+        i += 1
+    return out
+
+
 class BatchPlan:
-    """Plan for transforming many images of different sizes in one launch."""
+    """Plan for transforming many images of different sizes together: one
+    launch per (pass, stages, last-pass) class over every image."""
 
     def __init__(self, sizes, quads="full", in_dtype=torch.uint8, device=None):
         self.sizes = [(int(h), int(w)) for h, w in sizes]
