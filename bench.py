@@ -13,6 +13,8 @@ in HBM.  Prints one JSON line:
   fwd_adjoint   forward + adjoint (the backward of the transform)
   batched       8 such images through one batch plan (HIP graph replay),
                 beside a loop of 8 single-image forwards
+  sparse1024    1024^2 uint8: forward, forward + fused fhtshift, standalone
+                fhtshift, angle range [-15, 15] degrees (microseconds)
   batch512      512 uint8 images with sides uniform in 64..2048 (graph
                 replay), beside a loop of 512 single-image forwards
   cpu_baseline  the CPU oracle on this host's cores (bounded sample)
@@ -144,6 +146,34 @@ def bench_batch(fht, torch, imgs, steps, warmup, label):
     return res
 
 
+def bench_sparse1024(fht, synth, torch, steps):
+    """1024^2 uint8 image: full forward, forward with fhtshift fused into the
+    stores, standalone fhtshift of the full image, and the angle range
+    [-15, +15] degrees (int32 Hough images)."""
+    side = 1024
+    x = torch.from_numpy(synth.sparse1024(0)).cuda()
+    rows, cols = fht.hough_shape(side, side)
+    out = torch.empty((rows, cols), dtype=torch.int32, device="cuda")
+    out2 = torch.empty_like(out)
+    ws = torch.empty(max(fht.workspace_size(side, side, "full", torch.uint8), 256), dtype=torch.uint8, device="cuda")
+    S1, S = fht.range_params(side, -15.0, 15.0)
+    rr, rc = fht.range_shape(side, side, S1, S)
+    rout = torch.empty((rr, rc), dtype=torch.int32, device="cuda")
+    px = side * side
+    res = {"workload": "1024x1024 uint8, 2% of pixels uniform in 0..255 plus 8 lines of 255; int32 Hough images",
+           "unit": "microseconds per call"}
+    res["forward_us"] = round(_timed(lambda: fht.forward(x, out=out, workspace=ws), steps, 2, torch) * 1e3, 2)
+    res["forward_shifted_us"] = round(
+        _timed(lambda: fht.forward(x, shifted=True, out=out, workspace=ws), steps, 2, torch) * 1e3, 2)
+    res["fhtshift_us"] = round(_timed(lambda: fht.shift(out, side, side, out=out2), steps, 2, torch) * 1e3, 2)
+    res["range_us"] = round(_timed(lambda: fht.range_transform(x, S1, S, out=rout), steps, 2, torch) * 1e3, 2)
+    res["range"] = {"deg": [-15, 15], "S1": S1, "S": S, "rows": rr}
+    res["forward_gpx_s"] = round(px / (res["forward_us"] * 1e-6) / 1e9, 3)
+    log("sparse1024: forward %.1f us, shifted %.1f us, fhtshift %.1f us, range %.1f us"
+        % (res["forward_us"], res["forward_shifted_us"], res["fhtshift_us"], res["range_us"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +292,8 @@ def main():
         result["batched"] = bench_batch(fht, torch, imgs8, max(1, args.steps // 4), 1, "batched 8x4096^2 f32")
         result["batched"]["workload"] = "8 dense4096 images (seeds 0..7), float32"
         del imgs8
+
+        result["sparse1024"] = bench_sparse1024(fht, synth, torch, max(5, args.steps))
 
         imgs512 = [torch.from_numpy(a).cuda() for a in synth.batch512(0)]
         result["batch512"] = bench_batch(fht, torch, imgs512, 3, 1, "batch512 u8")

@@ -11,7 +11,6 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
 
 namespace fht {
 
@@ -212,7 +211,10 @@ PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int w, int h,
         d.dst = hough;
         d.dst_ld = ld_hough;
         d.dst_kind = DST_HOUGH;
-        d.x_start = 0;
+        // mirrored: the lane's run of xi = 8l + 1 .. 8l + 8 maps to x = -xi,
+        // a run starting on an 8-column (32-byte) boundary; unaligned vector
+        // stores cost about 1.7x as much
+        d.x_start = g.mirror ? 1 : 0;
         d.n_windows = (g.W + VW - 1) / VW;
         d.row_limit = row_limit_final;
         d.row_base = base;
@@ -334,17 +336,6 @@ int run_engine(const std::vector<EngineGroup>& groups, const EngineGroup* dev_ta
     return FHT_OK;
 }
 
-// FHT_ORDER: 0 = every quadrant's pass p in one launch, 2 = quadrant pairs.
-static int launch_order()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("FHT_ORDER");
-        v = e ? atoi(e) : 0;
-    }
-    return v;
-}
-
 // FHT_ENGINE=1 selects the persistent engine instead of one launch per pass.
 static bool use_engine()
 {
@@ -356,89 +347,10 @@ static bool use_engine()
     return v == 1;
 }
 
-// Side streams and events of the quadrant pipeline, one set per device.
-struct Pipeline {
-    bool ready = false;
-    hipStream_t s[4];
-    hipEvent_t start, p0_done[4], done[4];
-};
-static std::mutex g_pipe_mu;
-static Pipeline g_pipes[64];
-
-static int pipeline_for_current_device(Pipeline** out)
-{
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= 64) return fail(FHT_ERR_UNSUPPORTED, "device index %d", dev);
-    std::lock_guard<std::mutex> lock(g_pipe_mu);
-    Pipeline& P = g_pipes[dev];
-    if (!P.ready) {
-        // default-priority, non-blocking side streams; events without timing
-        for (int i = 0; i < 4; ++i) {
-            if ((e = hipStreamCreateWithFlags(&P.s[i], hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-            if ((e = hipEventCreateWithFlags(&P.p0_done[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-            if ((e = hipEventCreateWithFlags(&P.done[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-        }
-        if ((e = hipEventCreateWithFlags(&P.start, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-        P.ready = true;
-    }
-    *out = &P;
-    return FHT_OK;
-}
-
-static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t, unsigned* sync,
-                       hipStream_t stream);
-
-// Quadrant pipeline: quadrant i runs on its own stream and starts its first
-// pass when quadrant i-1's first pass is done, so at most two quadrants'
-// bands are live (they stay in the last-level cache between write and read)
-// while the passes of neighbouring quadrants overlap.  Forks from and joins
-// back to the caller's stream.
-static int run_forward_pipelined(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t,
-                                 unsigned* sync, hipStream_t stream)
-{
-    Pipeline* P = nullptr;
-    int rc = pipeline_for_current_device(&P);
-    if (rc) return rc;
-    hipError_t e = hipEventRecord(P->start, stream);
-    if (e != hipSuccess) return hip_fail(e, "event record");
-    for (int i = 0; i < nq; ++i) {
-        hipStream_t si = P->s[i];
-        if ((e = hipStreamWaitEvent(si, P->start, 0)) != hipSuccess) return hip_fail(e, "stream wait");
-        if (i > 0 && (e = hipStreamWaitEvent(si, P->p0_done[i - 1], 0)) != hipSuccess) return hip_fail(e, "stream wait");
-        for (int p = 0; p < gs[i].npass; ++p) {
-            PassLaunch L{};
-            L.d[0] = descs[i][p];
-            L.nd = 1;
-            if (gs[i].k <= 2) e = launch_direct(L, gs[i].k, in_t, acc_t, si);
-            else e = launch_pass(L, p == 0 ? in_t : acc_t, acc_t, si);
-            if (e != hipSuccess) return hip_fail(e, "pipelined pass launch");
-            if (p == 0 && (e = hipEventRecord(P->p0_done[i], si)) != hipSuccess) return hip_fail(e, "event record");
-        }
-        if ((e = hipEventRecord(P->done[i], si)) != hipSuccess) return hip_fail(e, "event record");
-    }
-    for (int i = 0; i < nq; ++i)
-        if ((e = hipStreamWaitEvent(stream, P->done[i], 0)) != hipSuccess) return hip_fail(e, "stream wait");
-    (void)sync;
-    return FHT_OK;
-}
-
 // Runs the forward passes of the quadrant geometries gs[0..nq).
 static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t, unsigned* sync,
                        hipStream_t stream)
 {
-    if (launch_order() == 3 && nq > 1 && !use_engine()) return run_forward_pipelined(gs, descs, nq, in_t, acc_t, sync, stream);
-    // quadrant pairs (1, 2) and (3, 4) one after the other: a pair's bands
-    // plus the image stay within the last-level cache between the passes
-    if (launch_order() == 2 && nq > 2) {
-        for (int i = 0; i < nq; i += 2) {
-            const int m = (nq - i) < 2 ? (nq - i) : 2;
-            int rc = run_forward(gs + i, descs + i, m, in_t, acc_t, sync, stream);
-            if (rc) return rc;
-        }
-        return FHT_OK;
-    }
     // quadrants with at most two stages: one direct launch
     for (int i = 0; i < nq; ++i) {
         if (gs[i].k > 2) continue;

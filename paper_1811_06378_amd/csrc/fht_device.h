@@ -498,6 +498,69 @@ __device__ __forceinline__ void fwd_phase_b(T (&a)[8][8], T (&b)[8][8], T* lds, 
     }
 }
 
+// Stores of one forward tile: rows of b to the band of the pass, or (last
+// pass) to the Hough image with the merged-row mapping, the mirror and the
+// optional fhtshift roll.
+template <typename T, int GB, bool LAST>
+__device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, int wave, int lane, const T (&b)[8][8])
+{
+    constexpr int G = 3 + GB;
+    constexpr int VW = kWinCols - (1 << G);
+    constexpr int NMINI = 1 << (6 - G);
+    const int j0 = d.j0;
+    const int n_mini = d.n >> G;
+    const int wc0 = 8 * lane;
+    if (wc0 >= VW) return;
+    const int xi = xi0 + wc0;  // xi of register 0
+    const int W = d.W;
+#pragma unroll
+    for (int rho = 0; rho < 8; ++rho) {
+        const int rp = rho & ((1 << GB) - 1);
+        const int q = rho >> GB;
+        const int kappa = (wave << (3 - GB)) + q;
+        const int t = kappa >> 3;
+        const int up = kappa & 7;
+        const int mu = rt * NMINI + t;
+        if (mu >= n_mini) continue;
+        const int B = mu >> j0;
+        const int u = mu & ((1 << j0) - 1);
+        const int s_local = (u << G) + (up << GB) + rp;
+        if (s_local > d.row_limit) continue;
+        const int out_row = (B << (j0 + G)) + s_local;
+        if constexpr (!LAST) {
+            T* dst = reinterpret_cast<T*>(d.dst) + (long long)out_row * d.dst_ld;
+            const int e0 = xi + d.dst_off;
+            if (e0 + 8 <= d.dst_bw) {
+                store8<T>(dst + e0, b[rho]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (e0 + c < d.dst_bw) dst[e0 + c] = b[rho][c];
+            }
+        } else {
+            const int s = out_row;
+            const int rel = xi - d.x_start;  // 0..W-1 over the windows
+            if (s == d.skip_row || rel >= W) continue;
+            T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
+            const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
+            // memory run of the lane's 8 columns (descending for mirrored quadrants)
+            const int e0 = d.mirror ? wrap_down(mod_w(-xi - 7 + roll, W), W) : wrap_up(mod_w(xi + roll, W), W);
+            if (rel + 8 <= W && e0 + 8 <= W) {
+                T v[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v[c] = d.mirror ? b[rho][7 - c] : b[rho][c];
+                if (d.stream_store) store8_stream<T>(dst + e0, v);
+                else store8<T>(dst + e0, v);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (rel + c < W) dst[run_col(e0, c, W, d.mirror)] = b[rho][c];
+            }
+        }
+    }
+}
+
+
 // One tile (64 rows x 512 columns) of one forward pass of G = 3 + GB stages.
 // rt: row tile, win: column window.  Every thread of the workgroup calls it.
 template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
@@ -576,55 +639,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         fwd_phase_b<T, GB>(a, b, lds, wave, lane);
     }
 
-    // ---- store
-    const int wc0 = 8 * lane;
-    if (wc0 >= VW) return;
-    const int xi = xi0 + wc0;  // xi of register 0
-    const int W = d.W;
-#pragma unroll
-    for (int rho = 0; rho < 8; ++rho) {
-        const int rp = rho & ((1 << GB) - 1);
-        const int q = rho >> GB;
-        const int kappa = (wave << (3 - GB)) + q;
-        const int t = kappa >> 3;
-        const int up = kappa & 7;
-        const int mu = rt * NMINI + t;
-        if (mu >= n_mini) continue;
-        const int B = mu >> j0;
-        const int u = mu & ((1 << j0) - 1);
-        const int s_local = (u << G) + (up << GB) + rp;
-        if (s_local > d.row_limit) continue;
-        const int out_row = (B << (j0 + G)) + s_local;
-        if constexpr (!LAST) {
-            T* dst = reinterpret_cast<T*>(d.dst) + (long long)out_row * d.dst_ld;
-            const int e0 = xi + d.dst_off;
-            if (e0 + 8 <= d.dst_bw) {
-                store8<T>(dst + e0, b[rho]);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (e0 + c < d.dst_bw) dst[e0 + c] = b[rho][c];
-            }
-        } else {
-            const int s = out_row;
-            if (s == d.skip_row || xi >= W) continue;
-            T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
-            const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
-            // memory run of the lane's 8 columns (descending for mirrored quadrants)
-            const int e0 = d.mirror ? wrap_down(mod_w(-xi - 7 + roll, W), W) : wrap_up(mod_w(xi + roll, W), W);
-            if (xi + 8 <= W && e0 + 8 <= W) {
-                T v[8];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) v[c] = d.mirror ? b[rho][7 - c] : b[rho][c];
-                if (d.stream_store) store8_stream<T>(dst + e0, v);
-                else store8<T>(dst + e0, v);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (xi + c < W) dst[run_col(e0, c, W, d.mirror)] = b[rho][c];
-            }
-        }
-    }
+    fwd_store<T, GB, LAST>(d, rt, xi0, wave, lane, b);
 }
 
 // Tile order.  Workgroups are dispatched to the 8 XCDs round-robin by block

@@ -2,6 +2,8 @@
 // launchers.
 #include "fht_launch.h"
 
+#include <cstdlib>
+
 namespace fht {
 
 __global__ void fht_zero_kernel(uint32_t* p, int64_t rows, int64_t cols_words, int64_t ld_words)
