@@ -24,4 +24,6 @@ from .oracle import (  # noqa: F401
     adjoint_quadrant,
     hough_shape,
     stacked_quadrants,
+    quadrant_op,
+    full_op,
 )

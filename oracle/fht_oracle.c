@@ -45,6 +45,11 @@
 #define ORACLE_BAD_ARG -1
 #define ORACLE_NO_MEMORY -2
 
+/* operation along the patterns: the sum of the paper, or max (section 1
+   notes the transform generalises to any associative, commutative op) */
+#define ORACLE_OP_SUM 0
+#define ORACLE_OP_MAX 1
+
 /* Threads the OpenMP loops use (1 without OpenMP). */
 int oracle_threads(void)
 {
@@ -119,7 +124,7 @@ static double src_value(const double* img, int64_t w, int64_t h, int64_t ld, int
  * out: n x W, row-major, n = h' (q=1,2) or w' (q=3,4).
  */
 static int quadrant_recurrence(const double* img, int64_t w, int64_t h, int64_t ld, int q,
-                               int single, const int64_t* pre_shift, double* out)
+                               int single, int op, const int64_t* pre_shift, double* out)
 {
     int64_t hp = oracle_next_pow2(h), wp = oracle_next_pow2(w);
     int64_t W = hp + wp;
@@ -149,8 +154,16 @@ static int quadrant_recurrence(const double* img, int64_t w, int64_t h, int64_t 
             int64_t off = dir * (t - sub);
             double* dst = b + row * W;
             for (int64_t x = 0; x < W; ++x) {
-                double v = top[x] + bot[mod_w(x + off, W)];
-                if (single) v = (double)(float)v;
+                double v;
+                if (op == ORACLE_OP_MAX) {
+                    /* section 1: the same patterns under another associative,
+                       commutative operation; max is exact in any precision */
+                    double u = bot[mod_w(x + off, W)];
+                    v = top[x] > u ? top[x] : u;
+                } else {
+                    v = top[x] + bot[mod_w(x + off, W)];
+                    if (single) v = (double)(float)v;
+                }
                 dst[x] = v;
             }
         }
@@ -162,18 +175,31 @@ static int quadrant_recurrence(const double* img, int64_t w, int64_t h, int64_t 
     return ORACLE_OK;
 }
 
-/* One quadrant, q in 1..4, out n x W (n = h' for q = 1, 2; w' for q = 3, 4). */
-int oracle_quadrant(const double* img, int64_t w, int64_t h, int64_t ld, int q, int single,
-                    double* out)
+static int quadrant_op(const double* img, int64_t w, int64_t h, int64_t ld, int q, int single, int op,
+                       double* out)
 {
     if (!img || !out || w < 1 || h < 1 || ld < w || q < 1 || q > 4) return ORACLE_BAD_ARG;
+    if (op != ORACLE_OP_SUM && op != ORACLE_OP_MAX) return ORACLE_BAD_ARG;
     if (single) {
         /* single-precision mode takes binary32 inputs */
         for (int64_t y = 0; y < h; ++y)
             for (int64_t x = 0; x < w; ++x)
                 if ((double)(float)img[y * ld + x] != img[y * ld + x]) return ORACLE_BAD_ARG;
     }
-    return quadrant_recurrence(img, w, h, ld, q, single, NULL, out);
+    return quadrant_recurrence(img, w, h, ld, q, single, op, NULL, out);
+}
+
+/* One quadrant, q in 1..4, out n x W (n = h' for q = 1, 2; w' for q = 3, 4). */
+int oracle_quadrant(const double* img, int64_t w, int64_t h, int64_t ld, int q, int single,
+                    double* out)
+{
+    return quadrant_op(img, w, h, ld, q, single, ORACLE_OP_SUM, out);
+}
+
+/* The same quadrant with op = ORACLE_OP_SUM (0) or ORACLE_OP_MAX (1). */
+int oracle_quadrant_op(const double* img, int64_t w, int64_t h, int64_t ld, int q, int op, double* out)
+{
+    return quadrant_op(img, w, h, ld, q, 0, op, out);
 }
 
 /*
@@ -181,7 +207,7 @@ int oracle_quadrant(const double* img, int64_t w, int64_t h, int64_t ld, int q, 
  * quadrant 3 flipped, quadrant 4, each join sharing one row (the shared rows
  * are equal, so the second copy is dropped).  out: (2(w'+h')-3) x W.
  */
-int oracle_full(const double* img, int64_t w, int64_t h, int64_t ld, int single, double* out)
+static int full_op(const double* img, int64_t w, int64_t h, int64_t ld, int single, int op, double* out)
 {
     if (!img || !out || w < 1 || h < 1 || ld < w) return ORACLE_BAD_ARG;
     int64_t hp = oracle_next_pow2(h), wp = oracle_next_pow2(w);
@@ -190,7 +216,7 @@ int oracle_full(const double* img, int64_t w, int64_t h, int64_t ld, int single,
     if (!hq) return ORACLE_NO_MEMORY;
     int64_t row = 0;
     for (int q = 1; q <= 4; ++q) {
-        int rc = oracle_quadrant(img, w, h, ld, q, single, hq);
+        int rc = quadrant_op(img, w, h, ld, q, single, op, hq);
         if (rc) { free(hq); return rc; }
         int64_t n = (q <= 2) ? hp : wp;
         int flip = (q == 1 || q == 3);
@@ -203,6 +229,17 @@ int oracle_full(const double* img, int64_t w, int64_t h, int64_t ld, int single,
     }
     free(hq);
     return ORACLE_OK;
+}
+
+int oracle_full(const double* img, int64_t w, int64_t h, int64_t ld, int single, double* out)
+{
+    return full_op(img, w, h, ld, single, ORACLE_OP_SUM, out);
+}
+
+/* Full image of the max transform (section 1): same layout, max for sum. */
+int oracle_full_op(const double* img, int64_t w, int64_t h, int64_t ld, int op, double* out)
+{
+    return full_op(img, w, h, ld, 0, op, out);
 }
 
 /*
@@ -289,7 +326,7 @@ int oracle_range(const double* img, int64_t w, int64_t h, int64_t ld, int64_t S1
     double* hq = (double*)malloc(sizeof(double) * (size_t)(n * W));
     if (!roll || !hq) { free(roll); free(hq); return ORACLE_NO_MEMORY; }
     for (int64_t y = 0; y < n; ++y) roll[y] = oracle_range_sigma(n, S1, y);
-    int rc = quadrant_recurrence(img, w, h, ld, transposed ? 4 : 1, single, roll, hq);
+    int rc = quadrant_recurrence(img, w, h, ld, transposed ? 4 : 1, single, ORACLE_OP_SUM, roll, hq);
     if (rc == ORACLE_OK) memcpy(out, hq, sizeof(double) * (size_t)((S + 1) * W));
     free(roll);
     free(hq);

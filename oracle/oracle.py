@@ -57,6 +57,10 @@ def _load():
             lib.oracle_quadrant.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD]
             lib.oracle_full.restype = ctypes.c_int
             lib.oracle_full.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, _PD]
+            lib.oracle_quadrant_op.restype = ctypes.c_int
+            lib.oracle_quadrant_op.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD]
+            lib.oracle_full_op.restype = ctypes.c_int
+            lib.oracle_full_op.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, _PD]
             lib.oracle_row_quadrant.restype = ctypes.c_int
             lib.oracle_row_quadrant.argtypes = [_I64, _I64, _I64, ctypes.POINTER(_I64)]
             lib.oracle_fhtshift_roll.restype = _I64
@@ -153,6 +157,31 @@ def full(img, single: bool = False) -> np.ndarray:
     _check_exact(a, max(next_pow2(h), next_pow2(w)))
     out = np.empty((rows, W), dtype=np.float64)
     _rc(_load().oracle_full(_ptr(a), w, h, w, int(single), _ptr(out)))
+    return out
+
+
+_OPS = {"sum": 0, "max": 1}
+
+
+def quadrant_op(img, q: int, op: str = "sum") -> np.ndarray:
+    """One quadrant with `op` along the patterns (section 1: any associative,
+    commutative operation; "max" here)."""
+    a = _as_f64(img)
+    h, w = a.shape
+    hp, wp = next_pow2(h), next_pow2(w)
+    n = hp if q <= 2 else wp
+    out = np.empty((n, hp + wp), dtype=np.float64)
+    _rc(_load().oracle_quadrant_op(_ptr(a), w, h, w, q, _OPS[op], _ptr(out)))
+    return out
+
+
+def full_op(img, op: str = "sum") -> np.ndarray:
+    """Full Hough image (section 3.3 layout) with `op` along the patterns."""
+    a = _as_f64(img)
+    h, w = a.shape
+    rows, W = hough_shape(w, h)
+    out = np.empty((rows, W), dtype=np.float64)
+    _rc(_load().oracle_full_op(_ptr(a), w, h, w, _OPS[op], _ptr(out)))
     return out
 
 

@@ -45,7 +45,9 @@ def padded(img: np.ndarray, transposed: bool) -> np.ndarray:
     return out
 
 
-def quadrant(img: np.ndarray, q: int) -> np.ndarray:
+def quadrant(img: np.ndarray, q: int, reduce=np.sum) -> np.ndarray:
+    """Every cell reduced directly over its pattern's pixels (np.sum, or
+    np.max for the max transform)."""
     transposed = q >= 3
     sign = 1 if q in (1, 4) else -1
     src = padded(np.asarray(img, dtype=np.float64), transposed)
@@ -56,12 +58,12 @@ def quadrant(img: np.ndarray, q: int) -> np.ndarray:
     for s in range(n):
         for x in range(W):
             cols = (x + sign * tab[s]) % W
-            out[s, x] = src[rows, cols].sum()
+            out[s, x] = reduce(src[rows, cols])
     return out
 
 
-def full(img: np.ndarray) -> np.ndarray:
-    h1, h2, h3, h4 = (quadrant(img, q) for q in (1, 2, 3, 4))
+def full(img: np.ndarray, reduce=np.sum) -> np.ndarray:
+    h1, h2, h3, h4 = (quadrant(img, q, reduce) for q in (1, 2, 3, 4))
     return np.concatenate([h1[::-1], h2[1:], h3[::-1][1:], h4[1:]], axis=0)
 
 

@@ -365,3 +365,49 @@ def test_paper_structure_fixture(oracle_mod):
         # roll of flipped quadrant 1: row 0 (shift h-1) by ~h, last row (shift 0) by h/2
         assert abs(oracle_mod.fhtshift_roll(1, h, w, h - 1) - eval(fx["fhtshift_q1_roll"]["row0"], env)) <= 1
         assert oracle_mod.fhtshift_roll(1, h, w, 0) == eval(fx["fhtshift_q1_roll"]["last_row"], env)
+
+
+# ---- the max transform (section 1: the transform generalises to any
+# associative, commutative operation along the same patterns)
+
+@pytest.mark.parametrize("h,w", [(1, 1), (3, 5), (8, 8), (7, 12), (16, 9)])
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_max_quadrant_matches_brute_force(oracle_mod, h, w, q):
+    img = _rand(h, w, seed=40 + q, lo=-5, hi=20)
+    np.testing.assert_array_equal(oracle_mod.quadrant_op(img, q, "max"), bf.quadrant(img, q, np.max))
+
+
+@pytest.mark.parametrize("h,w", [(8, 8), (5, 12), (16, 3)])
+def test_max_full_matches_brute_force(oracle_mod, h, w):
+    img = _rand(h, w, seed=9, lo=0, hi=30)
+    np.testing.assert_array_equal(oracle_mod.full_op(img, "max"), bf.full(img, np.max))
+
+
+def test_max_textbook_rows(oracle_mod):
+    """Shift 0 of the vertical quadrants is the column maximum of the padded
+    image; of the horizontal quadrants, the row maximum."""
+    img = _rand(12, 7, seed=3, lo=1, hi=50)
+    hp, wp = 16, 8
+    P = np.zeros((hp, hp + wp))
+    P[:12, :7] = img
+    np.testing.assert_array_equal(oracle_mod.quadrant_op(img, 1, "max")[0], P.max(axis=0))
+    Pt = np.zeros((wp, hp + wp))
+    Pt[:7, :12] = img.T
+    np.testing.assert_array_equal(oracle_mod.quadrant_op(img, 4, "max")[0], Pt.max(axis=0))
+
+
+def test_max_row_maximum_is_the_image_maximum(oracle_mod):
+    """For every shift the patterns x0 = 0..W-1 partition the padded image,
+    so the maximum over any Hough row is the maximum over the padded image."""
+    img = _rand(9, 13, seed=5, lo=-7, hi=7)
+    gmax = max(img.max(), 0.0)  # the zero padding takes part
+    for q in (1, 2, 3, 4):
+        H = oracle_mod.quadrant_op(img, q, "max")
+        np.testing.assert_array_equal(H.max(axis=1), np.full(H.shape[0], gmax))
+
+
+def test_max_of_binary_image_is_or(oracle_mod):
+    """On a 0/1 image max is the logical OR: a cell is 1 exactly when its
+    pattern's sum is positive."""
+    img = (np.random.default_rng(11).random((16, 16)) < 0.1).astype(np.float64)
+    np.testing.assert_array_equal(oracle_mod.full_op(img, "max"), (oracle_mod.full(img) > 0).astype(np.float64))
