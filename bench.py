@@ -259,7 +259,7 @@ def main():
     name, (launches, total_ms) = max(kernels.items(), key=lambda kv: kv[1][1])
     avg_ms = total_ms / launches
     alg = last_pass_algorithmic_bytes(fht, side, side, 4)
-    if "fht_pass_kernel<float, float, 3, false, true>" not in name:
+    if "fht_pass_kernel<float, float, 3, false, true, 0>" not in name:
         alg = None  # the byte formula below is that kernel's
     achieved = alg / (avg_ms * 1e-3) / 1e9 if alg else None
     result["roofline"] = {

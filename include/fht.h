@@ -70,8 +70,15 @@ enum fht_dtype { FHT_U8 = 0, FHT_I32 = 1, FHT_F32 = 2 };
  * unmerged and unflipped, stacked in increasing quadrant order. */
 enum { FHT_Q1 = 1, FHT_Q2 = 2, FHT_Q3 = 4, FHT_Q4 = 8, FHT_FULL = 15 };
 
-/* fht_forward / fht_adjoint flags. */
-enum { FHT_FLAG_SHIFTED = 1 }; /* output (forward) or input (adjoint) is fhtshift-ed */
+/* fht_forward / fht_adjoint flags.
+ * FHT_FLAG_SHIFTED: output (forward) or input (adjoint) is fhtshift-ed.
+ * FHT_FLAG_MAX (fht_forward only): each Hough cell is the maximum, not the
+ *   sum, of the padded image along its pattern; the transform generalises to
+ *   any associative, commutative operation (section 1).  Same patterns, same
+ *   shapes and layout; the zero padding takes part in the maximum, and on a
+ *   0/1 image the result is the logical OR.  Exact in every dtype.  The
+ *   adjoint rejects it (FHT_ERR_INVALID). */
+enum { FHT_FLAG_SHIFTED = 1, FHT_FLAG_MAX = 2 };
 
 /* Largest supported side (pow2-padded): 65536. */
 #define FHT_MAX_SIDE 65536
@@ -104,7 +111,7 @@ int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* byte
 
 /*
  * Forward FHT (sections 3.1 and 3.3; fhtshift of section 5 with
- * FHT_FLAG_SHIFTED).
+ * FHT_FLAG_SHIFTED; the max transform of section 1 with FHT_FLAG_MAX).
  *   img       device, h x w elements of in_t, row pitch ld_img >= w (elements)
  *   hough     device, rows x cols of acc_t from fht_hough_shape, row pitch
  *             ld_hough >= cols; every cell is written

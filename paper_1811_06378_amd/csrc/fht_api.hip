@@ -348,8 +348,9 @@ static bool use_engine()
 }
 
 // Runs the forward passes of the quadrant geometries gs[0..nq).
+// op: 0 = sum along the patterns, 1 = max.
 static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t, unsigned* sync,
-                       hipStream_t stream)
+                       hipStream_t stream, int op = 0)
 {
     // quadrants with at most two stages: one direct launch
     for (int i = 0; i < nq; ++i) {
@@ -357,10 +358,10 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
         PassLaunch L{};
         L.d[0] = descs[i][0];
         L.nd = 1;
-        hipError_t e = launch_direct(L, gs[i].k, in_t, acc_t, stream);
+        hipError_t e = launch_direct(L, gs[i].k, in_t, acc_t, stream, op);
         if (e != hipSuccess) return hip_fail(e, "direct launch");
     }
-    if (use_engine()) {
+    if (use_engine() && op == 0) {
         std::vector<EngineGroup> groups;
         const int total = append_engine_groups(gs, descs, nq, groups, 0);
         return run_engine(groups, nullptr, total, sync, in_t, acc_t, stream);
@@ -376,7 +377,7 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
                         L.d[L.nd++] = descs[i][p];
                 if (L.nd == 0) continue;
                 const int ti = p == 0 ? in_t : acc_t;
-                hipError_t e = launch_pass(L, ti, acc_t, stream);
+                hipError_t e = launch_pass(L, ti, acc_t, stream, op);
                 if (e != hipSuccess) return hip_fail(e, "forward pass launch");
             }
         }
@@ -511,7 +512,7 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
     if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
     if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
     if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
-    if (flags & ~(unsigned)FHT_FLAG_SHIFTED) return fail(FHT_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (flags & ~(unsigned)(FHT_FLAG_SHIFTED | FHT_FLAG_MAX)) return fail(FHT_ERR_INVALID, "unknown flags 0x%x", flags);
     if ((flags & FHT_FLAG_SHIFTED) && quads != FHT_FULL)
         return fail(FHT_ERR_INVALID, "fhtshift applies to the full Hough image only");
     int qs[4];
@@ -530,7 +531,8 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
             descs[i][p] = make_pass_desc(gs[i], p, img, w, h, ld_img, hough, ld_hough, (unsigned char*)workspace, 0,
                                          INT_MAX, base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb);
     }
-    return run_forward(gs, descs, nq, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream);
+    return run_forward(gs, descs, nq, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream,
+                       (flags & FHT_FLAG_MAX) ? 1 : 0);
 }
 
 int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, int S, int transposed, void* hough,
@@ -647,6 +649,7 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "adjoint type must be I32 or F32");
     if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
     if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
+    if (flags & FHT_FLAG_MAX) return fail(FHT_ERR_INVALID, "the adjoint is the transpose of the sum transform");
     if (flags & ~(unsigned)FHT_FLAG_SHIFTED) return fail(FHT_ERR_INVALID, "unknown flags 0x%x", flags);
     if ((flags & FHT_FLAG_SHIFTED) && quads != FHT_FULL)
         return fail(FHT_ERR_INVALID, "fhtshift applies to the full Hough image only");

@@ -228,7 +228,17 @@ __device__ __forceinline__ const T* zero_page()
 // and 2i+1 both come from the pair (top row i, bottom row 2^J + i), the
 // bottom one shifted by i and i+1 columns.  Each output pair depends on one
 // input pair only: the stage is a set of row butterflies.
-template <typename T, int J>
+// The operation along the patterns: 0 = sum (the transform), 1 = max (the
+// same patterns under another associative, commutative operation, section 1).
+template <int OP, typename T>
+__device__ __forceinline__ T combine(T x, T y)
+{
+    if constexpr (OP == 0) return x + y;
+    else if constexpr (sizeof(T) == 4 && T(0.5) != T(0)) return __builtin_fmaxf(x, y);
+    else return x > y ? x : y;
+}
+
+template <typename T, int J, int OP = 0>
 __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
 {
     constexpr int H = 1 << J;
@@ -242,8 +252,8 @@ __device__ __forceinline__ void fwd_stage(T (&a)[8][8])
                 const int c0 = c + i, c1 = c + i + 1;
                 const T b0 = c0 >= 8 ? dpp_move<kDppFromNext>(a[blk + H + i][c0 - 8]) : a[blk + H + i][c0];
                 const T b1 = c1 >= 8 ? dpp_move<kDppFromNext>(a[blk + H + i][c1 - 8]) : a[blk + H + i][c1];
-                o[blk + 2 * i][c] = a[blk + i][c] + b0;
-                o[blk + 2 * i + 1][c] = a[blk + i][c] + b1;
+                o[blk + 2 * i][c] = combine<OP>(a[blk + i][c], b0);
+                o[blk + 2 * i + 1][c] = combine<OP>(a[blk + i][c], b1);
             }
         }
     }
@@ -286,12 +296,12 @@ __device__ __forceinline__ void adj_stage(T (&a)[8][8])
         for (int c = 0; c < 8; ++c) a[r][c] = o[r][c];
 }
 
-template <typename T, int GB>
+template <typename T, int GB, int OP = 0>
 __device__ __forceinline__ void fwd_stages_b(T (&b)[8][8])
 {
-    if constexpr (GB > 0) fwd_stage<T, 0>(b);
-    if constexpr (GB > 1) fwd_stage<T, 1>(b);
-    if constexpr (GB > 2) fwd_stage<T, 2>(b);
+    if constexpr (GB > 0) fwd_stage<T, 0, OP>(b);
+    if constexpr (GB > 1) fwd_stage<T, 1, OP>(b);
+    if constexpr (GB > 2) fwd_stage<T, 2, OP>(b);
 }
 
 template <typename T, int GB>
@@ -459,7 +469,7 @@ __device__ __forceinline__ void load_rows_transposed(const PassDesc& d, int R0, 
 // Phase B of a forward tile for GB = G - 3 stages after the exchange.  The
 // exchange runs in two halves (registers 0-3, then 4-7 of every wave) so the
 // LDS holds 32 rows and two workgroups fit on a CU.
-template <typename T, int GB>
+template <typename T, int GB, int OP = 0>
 __device__ __forceinline__ void fwd_phase_b(T (&a)[8][8], T (&b)[8][8], T* lds, int wave, int lane)
 {
     if constexpr (GB == 0) {
@@ -494,7 +504,7 @@ __device__ __forceinline__ void fwd_phase_b(T (&a)[8][8], T (&b)[8][8], T* lds, 
             }
             if (h == 0) __syncthreads();
         }
-        fwd_stages_b<T, GB>(b);
+        fwd_stages_b<T, GB, OP>(b);
     }
 }
 
@@ -563,7 +573,7 @@ __device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, in
 
 // One tile (64 rows x 512 columns) of one forward pass of G = 3 + GB stages.
 // rt: row tile, win: column window.  Every thread of the workgroup calls it.
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP = 0>
 __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* lds)
 {
     constexpr int G = 3 + GB;
@@ -632,11 +642,11 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                 }
             }
         }
-        fwd_stage<T, 0>(a);
-        fwd_stage<T, 1>(a);
-        fwd_stage<T, 2>(a);
+        fwd_stage<T, 0, OP>(a);
+        fwd_stage<T, 1, OP>(a);
+        fwd_stage<T, 2, OP>(a);
         // ---- phase B: rows 8g + u' read with offsets u'*g, last GB stages
-        fwd_phase_b<T, GB>(a, b, lds, wave, lane);
+        fwd_phase_b<T, GB, OP>(a, b, lds, wave, lane);
     }
 
     fwd_store<T, GB, LAST>(d, rt, xi0, wave, lane, b);
@@ -654,7 +664,7 @@ __device__ __forceinline__ int xcd_tile(int block, int n_tiles)
     return (block % kXcds) * per + block / kXcds;
 }
 
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP>
 __global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch L)
 {
     __shared__ T lds[kTileRows / 2 * kLdsRow];
@@ -667,7 +677,7 @@ __global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch 
     }
     const PassDesc& d = L.d[z];
     const int rt = t / d.n_windows;
-    fwd_tile<TIn, T, GB, FIRST, LAST>(d, rt, t - rt * d.n_windows, lds);
+    fwd_tile<TIn, T, GB, FIRST, LAST, OP>(d, rt, t - rt * d.n_windows, lds);
 }
 
 // Many passes (of many images) of one kind in one launch: block -> item ->
@@ -1062,7 +1072,7 @@ __device__ __forceinline__ T src_value(const PassDesc& d, int R, int x)
 
 // The same add tree as K stages of the recurrence, evaluated top-down in x
 // (direction -1 for mirrored quadrants).
-template <typename TIn, typename T, int K>
+template <typename TIn, typename T, int K, int OP>
 __device__ T direct_sum(const PassDesc& d, int base, int s, int x)
 {
     if constexpr (K == 0) {
@@ -1070,21 +1080,21 @@ __device__ T direct_sum(const PassDesc& d, int base, int s, int x)
     } else {
         const int sub = s >> 1;
         const int dir = d.mirror ? -1 : 1;
-        const T top = direct_sum<TIn, T, K - 1>(d, base, sub, x);
-        const T bot = direct_sum<TIn, T, K - 1>(d, base + (1 << (K - 1)), sub,
-                                               mod_pos((long long)x + dir * (s - sub), d.W));
-        return top + bot;
+        const T top = direct_sum<TIn, T, K - 1, OP>(d, base, sub, x);
+        const T bot = direct_sum<TIn, T, K - 1, OP>(d, base + (1 << (K - 1)), sub,
+                                                   mod_pos((long long)x + dir * (s - sub), d.W));
+        return combine<OP>(top, bot);
     }
 }
 
-template <typename TIn, typename T, int K>
+template <typename TIn, typename T, int K, int OP>
 __global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
 {
     const PassDesc& d = L.d[blockIdx.z];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (x >= d.W || s >= d.n || s > d.row_limit || s == d.skip_row) return;
-    const T v = direct_sum<TIn, T, K>(d, 0, s, x);
+    const T v = direct_sum<TIn, T, K, OP>(d, 0, s, x);
     T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
     const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
     dst[mod_pos((long long)x + roll, d.W)] = v;

@@ -113,8 +113,9 @@ struct EngineArgs {
 
 inline size_t engine_sync_bytes(int n_groups) { return ((size_t)(n_groups + 2) * 4 + 255) / 256 * 256; }
 
-hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s);
-hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s);
+// op: 0 = sum along the patterns, 1 = max
+hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s, int op = 0);
+hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s, int op = 0);
 hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc_t, hipStream_t s);
 // table: device array of n_groups groups of one kind (same G, first/last)
 hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int in_t,
@@ -127,9 +128,10 @@ hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out
 int engine_grid_size();
 
 // Launch timing (fht_timing_enable): the rocprof-style name of a pass kernel
-// instantiation (in_t < 0: adjoint kernels, one type), and the event pair
+// instantiation (in_t < 0: adjoint kernels, one type; op >= 0: the forward
+// pass kernel's trailing operation argument), and the event pair
 // around one launch.  timing_begin returns -1 when timing is off.
-std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last);
+std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last, int op = -1);
 bool timing_on();
 int timing_begin(const std::string& name, hipStream_t s);
 void timing_end(int slot, hipStream_t s);

@@ -7,7 +7,7 @@
 
 namespace fht {
 
-template <typename TIn, typename T, int GB>
+template <typename TIn, typename T, int GB, int OP>
 hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
 {
     PassLaunch L = L0;
@@ -16,22 +16,22 @@ hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
     if (L.n_tiles == 0) return hipSuccess;
     const bool first = L.d[0].src_kind != SRC_BAND, last = L.d[0].dst_kind == DST_HOUGH;
     const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds);
-    if (first && last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true>), grid, dim3(kThreads), 0, s, L);
-    else if (first) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false>), grid, dim3(kThreads), 0, s, L);
-    else if (last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true>), grid, dim3(kThreads), 0, s, L);
-    else hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false>), grid, dim3(kThreads), 0, s, L);
+    if (first && last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP>), grid, dim3(kThreads), 0, s, L);
+    else if (first) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP>), grid, dim3(kThreads), 0, s, L);
+    else if (last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true, OP>), grid, dim3(kThreads), 0, s, L);
+    else hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false, OP>), grid, dim3(kThreads), 0, s, L);
     return hipGetLastError();
 }
 
 // all descriptors of one launch share G and first/last
-template <typename TIn, typename T>
+template <typename TIn, typename T, int OP = 0>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t s)
 {
     switch (L.d[0].G) {
-    case 3: return launch_pass_g<TIn, T, 0>(L, s);
-    case 4: return launch_pass_g<TIn, T, 1>(L, s);
-    case 5: return launch_pass_g<TIn, T, 2>(L, s);
-    case 6: return launch_pass_g<TIn, T, 3>(L, s);
+    case 3: return launch_pass_g<TIn, T, 0, OP>(L, s);
+    case 4: return launch_pass_g<TIn, T, 1, OP>(L, s);
+    case 5: return launch_pass_g<TIn, T, 2, OP>(L, s);
+    case 6: return launch_pass_g<TIn, T, 3, OP>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -85,7 +85,7 @@ hipError_t launch_engine_t(const EngineArgs& A, int G, int grid, hipStream_t s)
     }
 }
 
-template <typename TIn, typename T>
+template <typename TIn, typename T, int OP = 0>
 hipError_t launch_direct_t(const PassLaunch& L, int k, hipStream_t s)
 {
     int W = 1, n = 1;
@@ -95,9 +95,9 @@ hipError_t launch_direct_t(const PassLaunch& L, int k, hipStream_t s)
     }
     const dim3 grid((W + 255) / 256, n, L.nd);
     switch (k) {
-    case 0: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 0>), grid, dim3(256), 0, s, L); break;
-    case 1: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 1>), grid, dim3(256), 0, s, L); break;
-    case 2: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 2>), grid, dim3(256), 0, s, L); break;
+    case 0: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 0, OP>), grid, dim3(256), 0, s, L); break;
+    case 1: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 1, OP>), grid, dim3(256), 0, s, L); break;
+    case 2: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 2, OP>), grid, dim3(256), 0, s, L); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -155,6 +155,8 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
 // per-type entry points (defined in the instantiation units)
 #define FHT_DECLARE_FWD(name)                                                   \
     hipError_t launch_pass_##name(const PassLaunch& L, hipStream_t s);           \
+    hipError_t launch_pass_max_##name(const PassLaunch& L, hipStream_t s);       \
+    hipError_t launch_direct_max_##name(const PassLaunch& L, int k, hipStream_t s); \
     hipError_t launch_engine_##name(const EngineArgs& A, int G, int grid, hipStream_t s); \
     hipError_t launch_direct_##name(const PassLaunch& L, int k, hipStream_t s);                 \
     hipError_t launch_table_##name(const EngineGroup* table, int n_groups, int n_items, int G, bool first, \

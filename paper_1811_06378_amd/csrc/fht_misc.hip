@@ -17,21 +17,28 @@ __global__ void fht_zero_kernel(uint32_t* p, int64_t rows, int64_t cols_words, i
 }
 
 // dtype codes: 0 = u8, 1 = i32, 2 = f32
-static hipError_t launch_pass_typed(const PassLaunch& L, int in_t, int acc_t, hipStream_t s)
+static hipError_t launch_pass_typed(const PassLaunch& L, int in_t, int acc_t, int op, hipStream_t s)
 {
+    if (op == 1) {
+        if (in_t == 0 && acc_t == 1) return launch_pass_max_u8(L, s);
+        if (in_t == 1 && acc_t == 1) return launch_pass_max_i32(L, s);
+        if (in_t == 2 && acc_t == 2) return launch_pass_max_f32(L, s);
+        return hipErrorInvalidValue;
+    }
+    if (op != 0) return hipErrorInvalidValue;
     if (in_t == 0 && acc_t == 1) return launch_pass_u8(L, s);
     if (in_t == 1 && acc_t == 1) return launch_pass_i32(L, s);
     if (in_t == 2 && acc_t == 2) return launch_pass_f32(L, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s)
+hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s, int op)
 {
     int slot = -1;
     if (timing_on())
         slot = timing_begin(kernel_name("fht_pass_kernel", in_t, acc_t, L.d[0].G - 3, L.d[0].src_kind != SRC_BAND,
-                                        L.d[0].dst_kind == DST_HOUGH), s);
-    const hipError_t e = launch_pass_typed(L, in_t, acc_t, s);
+                                        L.d[0].dst_kind == DST_HOUGH, op), s);
+    const hipError_t e = launch_pass_typed(L, in_t, acc_t, op, s);
     timing_end(slot, s);
     return e;
 }
@@ -63,8 +70,15 @@ hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int
     return e;
 }
 
-hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s)
+hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s, int op)
 {
+    if (op == 1) {
+        if (in_t == 0 && acc_t == 1) return launch_direct_max_u8(L, k, s);
+        if (in_t == 1 && acc_t == 1) return launch_direct_max_i32(L, k, s);
+        if (in_t == 2 && acc_t == 2) return launch_direct_max_f32(L, k, s);
+        return hipErrorInvalidValue;
+    }
+    if (op != 0) return hipErrorInvalidValue;
     if (in_t == 0 && acc_t == 1) return launch_direct_u8(L, k, s);
     if (in_t == 1 && acc_t == 1) return launch_direct_i32(L, k, s);
     if (in_t == 2 && acc_t == 2) return launch_direct_f32(L, k, s);

@@ -53,15 +53,17 @@ int class_of(const std::string& name)
 
 }  // namespace
 
-std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last)
+std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last, int op)
 {
     char buf[160];
+    char tail[16] = "";
+    if (op >= 0) snprintf(tail, sizeof tail, ", %d", op);
     if (in_t < 0)
-        snprintf(buf, sizeof buf, "fht::%s<%s, %d, %s, %s>", kernel, type_name(acc_t), GB, first ? "true" : "false",
-                 last ? "true" : "false");
+        snprintf(buf, sizeof buf, "fht::%s<%s, %d, %s, %s%s>", kernel, type_name(acc_t), GB, first ? "true" : "false",
+                 last ? "true" : "false", tail);
     else
-        snprintf(buf, sizeof buf, "fht::%s<%s, %s, %d, %s, %s>", kernel, type_name(in_t), type_name(acc_t), GB,
-                 first ? "true" : "false", last ? "true" : "false");
+        snprintf(buf, sizeof buf, "fht::%s<%s, %s, %d, %s, %s%s>", kernel, type_name(in_t), type_name(acc_t), GB,
+                 first ? "true" : "false", last ? "true" : "false", tail);
     return buf;
 }
 

@@ -5,7 +5,8 @@ memory (tensors) and the current HIP stream.  If the library is missing the
 calls raise instead of falling back to anything else.
 
 Names follow the C ABI in include/fht.h:
-  forward(img, quads='full', shifted=False)   sections 3.1, 3.3 (and 5)
+  forward(img, quads='full', shifted=False, op='sum')
+                                              sections 3.1, 3.3 (and 5; op='max': section 1)
   range_transform(img, S1, S, transposed)     section 4
   shift(hough, w, h, inverse)                 section 5 (fhtshift)
   adjoint(grad, w, h, quads, shifted)         transpose of forward
@@ -28,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libfht.so")
 FHT_OK, FHT_ERR_INVALID, FHT_ERR_UNSUPPORTED, FHT_ERR_WORKSPACE, FHT_ERR_HIP, FHT_ERR_TIMEOUT = 0, -1, -2, -3, -4, -5
 FHT_U8, FHT_I32, FHT_F32 = 0, 1, 2
 FHT_Q1, FHT_Q2, FHT_Q3, FHT_Q4, FHT_FULL = 1, 2, 4, 8, 15
-FHT_FLAG_SHIFTED = 1
+FHT_FLAG_SHIFTED, FHT_FLAG_MAX = 1, 2
 
 _lock = threading.Lock()
 _lib = None
@@ -172,8 +173,12 @@ def workspace_size(w: int, h: int, quads="full", in_dtype=torch.float32) -> int:
 
 
 def forward(img: torch.Tensor, quads="full", shifted: bool = False, out: torch.Tensor | None = None,
-            workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """Hough image of a 2-D device image (uint8 -> int32, int32, float32)."""
+            workspace: torch.Tensor | None = None, op: str = "sum") -> torch.Tensor:
+    """Hough image of a 2-D device image (uint8 -> int32, int32, float32).
+    op="max" takes the maximum along every pattern instead of the sum
+    (section 1: any associative, commutative operation)."""
+    if op not in ("sum", "max"):
+        raise ValueError("op must be 'sum' or 'max'")
     _check_2d(img, "img")
     h, w = img.shape
     it, at, odt = _dtypes(img.dtype)
@@ -187,8 +192,9 @@ def forward(img: torch.Tensor, quads="full", shifted: bool = False, out: torch.T
     nb = workspace_size(w, h, q, img.dtype)
     if workspace is None:
         workspace = _workspace(nb, img.device)
+    flags = (FHT_FLAG_SHIFTED if shifted else 0) | (FHT_FLAG_MAX if op == "max" else 0)
     rc = lib().fht_forward(img.data_ptr(), it, w, h, img.stride(0), out.data_ptr(), at, out.stride(0), q,
-                           FHT_FLAG_SHIFTED if shifted else 0, workspace.data_ptr(),
+                           flags, workspace.data_ptr(),
                            workspace.numel() * workspace.element_size(), _stream())
     _check(rc, "fht_forward")
     return out

@@ -101,6 +101,9 @@ def test_validation_before_hip():
     assert L.fht_range(dummy, 0, 64, 64, 64, 0, 64, 0, dummy, 1, 128, None, 0, s) == fht.FHT_ERR_INVALID
     # adjoint type
     assert L.fht_adjoint(dummy, 0, 16, dummy, 8, 8, 8, 15, 0, None, 0, s) == fht.FHT_ERR_INVALID
+    # the max transform has no adjoint; unknown flag bits are rejected
+    assert L.fht_adjoint(dummy, 2, 16, dummy, 8, 8, 8, 15, fht.FHT_FLAG_MAX, None, 0, s) == fht.FHT_ERR_INVALID
+    assert L.fht_forward(dummy, 2, 8, 8, 8, dummy, 2, 16, 15, 4, None, 0, s) == fht.FHT_ERR_INVALID
     # fhtshift overlap that is not identity
     assert L.fht_shift(dummy, 16, ctypes.c_void_p(0x1004), 16, 2, 8, 8, 0, s) == fht.FHT_ERR_INVALID
     # batch: bad sizes
