@@ -26,4 +26,5 @@ from .oracle import (  # noqa: F401
     stacked_quadrants,
     quadrant_op,
     full_op,
+    range_adjoint,
 )

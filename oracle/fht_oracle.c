@@ -456,6 +456,40 @@ int oracle_adjoint_full(const double* g, int64_t w, int64_t h, int single, doubl
     return ORACLE_OK;
 }
 
+/*
+ * Adjoint of the angle-range transform (section 4).  The range output is rows
+ * 0..S of quadrant 1 (4 when transposed) of the padded source whose row r is
+ * rolled right by sigma(r); so the gradient rows 0..S (rows S+1..n-1 get
+ * none) go back through the transposed stages to that sheared source, whose
+ * cell (r, xi) is the source cell (r, xi - sigma(r)); the result is cropped
+ * to the h x w image (transposed back for the mostly-horizontal variant).
+ * g: (S+1) x W;  out: h x w, row-major with ld_out.
+ */
+int oracle_range_adjoint(const double* g, int64_t w, int64_t h, int64_t S1, int64_t S, int transposed,
+                         int single, double* out, int64_t ld_out)
+{
+    if (!g || !out || w < 1 || h < 1 || ld_out < w) return ORACLE_BAD_ARG;
+    int64_t hp = oracle_next_pow2(h), wp = oracle_next_pow2(w);
+    int64_t W = hp + wp;
+    int64_t n = transposed ? wp : hp;
+    if (S < 0 || S > n - 1 || S1 > n - 1 || S1 < -(n - 1)) return ORACLE_BAD_ARG;
+    double* slab = (double*)calloc((size_t)(n * W), sizeof(double));
+    double* src = (double*)malloc(sizeof(double) * (size_t)(n * W));
+    if (!slab || !src) { free(slab); free(src); return ORACLE_NO_MEMORY; }
+    memcpy(slab, g, sizeof(double) * (size_t)((S + 1) * W));
+    int rc = quadrant_adjoint(slab, n, W, +1, single, src);
+    if (rc == ORACLE_OK)
+        for (int64_t y = 0; y < h; ++y)
+            for (int64_t x = 0; x < w; ++x) {
+                int64_t r = transposed ? x : y;     /* source row (image row, or column) */
+                int64_t c = transposed ? y : x;     /* source column */
+                out[y * ld_out + x] = src[r * W + mod_w(c + oracle_range_sigma(n, S1, r), W)];
+            }
+    free(slab);
+    free(src);
+    return rc;
+}
+
 /* Adjoint of one quadrant alone (gradient n x W) onto the h x w image. */
 int oracle_adjoint_quadrant(const double* g, int64_t w, int64_t h, int q, int single, double* out,
                             int64_t ld_out)

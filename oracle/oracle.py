@@ -57,6 +57,9 @@ def _load():
             lib.oracle_quadrant.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD]
             lib.oracle_full.restype = ctypes.c_int
             lib.oracle_full.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, _PD]
+            lib.oracle_range_adjoint.restype = ctypes.c_int
+            lib.oracle_range_adjoint.argtypes = [_PD, _I64, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD,
+                                                 _I64]
             lib.oracle_quadrant_op.restype = ctypes.c_int
             lib.oracle_quadrant_op.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD]
             lib.oracle_full_op.restype = ctypes.c_int
@@ -157,6 +160,14 @@ def full(img, single: bool = False) -> np.ndarray:
     _check_exact(a, max(next_pow2(h), next_pow2(w)))
     out = np.empty((rows, W), dtype=np.float64)
     _rc(_load().oracle_full(_ptr(a), w, h, w, int(single), _ptr(out)))
+    return out
+
+
+def range_adjoint(g, w: int, h: int, S1: int, S: int, transposed: bool = False, single: bool = False) -> np.ndarray:
+    """Adjoint of range_transform (section 4): (S+1) x W gradient -> h x w."""
+    a = _as_f64(g)
+    out = np.empty((h, w), dtype=np.float64)
+    _rc(_load().oracle_range_adjoint(_ptr(a), w, h, S1, S, int(transposed), int(single), _ptr(out), w))
     return out
 
 

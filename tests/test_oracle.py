@@ -411,3 +411,35 @@ def test_max_of_binary_image_is_or(oracle_mod):
     pattern's sum is positive."""
     img = (np.random.default_rng(11).random((16, 16)) < 0.1).astype(np.float64)
     np.testing.assert_array_equal(oracle_mod.full_op(img, "max"), (oracle_mod.full(img) > 0).astype(np.float64))
+
+
+# ---- adjoint of the angle-range transform (section 4)
+
+RANGE_CASES = [(8, 8, 0, 7, False), (8, 8, 3, 6, False), (16, 12, -5, 9, False), (13, 16, 7, 15, False),
+               (16, 16, -15, 15, False), (12, 7, 2, 5, True), (9, 16, -3, 4, True), (8, 16, 0, 15, True)]
+
+
+@pytest.mark.parametrize("h,w,S1,S,tr", RANGE_CASES)
+def test_range_adjoint_inner_product_identity(oracle_mod, h, w, S1, S, tr):
+    """<R x, g> = <x, R^T g> exactly on integers, R the (brute-force pinned)
+    range transform."""
+    rng = np.random.default_rng(h * 31 + w + S1)
+    x = rng.integers(-50, 51, size=(h, w)).astype(np.float64)
+    Rx = oracle_mod.range_transform(x, S1, S, tr)
+    g = rng.integers(-50, 51, size=Rx.shape).astype(np.float64)
+    lhs = int(np.sum(Rx.astype(np.int64) * g.astype(np.int64)))
+    rhs = int(np.sum(x.astype(np.int64) * oracle_mod.range_adjoint(g, w, h, S1, S, tr).astype(np.int64)))
+    assert lhs == rhs
+
+
+def test_range_adjoint_unsheared_full_range_is_the_quadrant_adjoint(oracle_mod):
+    """S1 = 0, S = n - 1: the range is quadrant 1 (4 when transposed), so its
+    adjoint is the quadrant adjoint."""
+    rng = np.random.default_rng(2)
+    h, w = 16, 11
+    g1 = rng.integers(-9, 10, size=(16, 32)).astype(np.float64)
+    np.testing.assert_array_equal(oracle_mod.range_adjoint(g1, w, h, 0, 15, False),
+                                  oracle_mod.adjoint_quadrant(g1, w, h, 1))
+    g4 = rng.integers(-9, 10, size=(16, 32)).astype(np.float64)
+    np.testing.assert_array_equal(oracle_mod.range_adjoint(g4, w, h, 0, 15, True),
+                                  oracle_mod.adjoint_quadrant(g4, w, h, 4))
