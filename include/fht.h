@@ -168,6 +168,21 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 void* stream);
 
 /*
+ * Adjoint of fht_range (transpose of the angle-range transform of section 4):
+ * the gradient of rows 0..S goes back through the transposed stages to the
+ * padded source sheared by sigma(y), is read back at the unsheared columns,
+ * and is cropped to the image (transposed back when transposed = 1).
+ *   grad      device, (S+1) x W of t (FHT_I32 or FHT_F32), row pitch ld_grad
+ *   grad_img  device, h x w of t, row pitch ld_img >= w; overwritten
+ *   workspace >= fht_range_adjoint_workspace_size bytes, 256-byte aligned
+ * Same S1, S, transposed limits as fht_range; grad and grad_img must not
+ * overlap.  Integer gradients are exact: <R x, g> = <x, R^T g>.
+ */
+int fht_range_adjoint_workspace_size(int w, int h, int S1, int S, int transposed, int t, size_t* bytes);
+int fht_range_adjoint(const void* grad, int t, int64_t ld_grad, int S1, int S, int transposed, void* grad_img,
+                      int64_t ld_img, int w, int h, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Batched forward over many images of different sizes (many independent
  * transforms of sections 3.1 and 3.3).  Each image is transformed as by
  * fht_forward(quads, flags = 0) into its own slice of one packed output

@@ -588,6 +588,7 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
     AdjDesc d{};
     const int G = g.G[p];
     const int VW = kWinCols - (1 << G);
+    d.row_limit = INT_MAX;  // every Hough row is read (angle range: set to S)
     d.n = g.n;
     d.W = g.W;
     d.j0 = p == 0 ? 0 : g.j_end[p - 1];
@@ -699,6 +700,71 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
             }
         }
     }
+    return FHT_OK;
+}
+
+// Angle-range adjoint: the bands of the range's quadrant geometry, then the
+// n x W gradient of the sheared padded source.
+static size_t range_adjoint_workspace(QuadGeom& g)
+{
+    const size_t bands = layout_bands(&g, 1, 4, 0);
+    return bands + ((size_t)g.n * (size_t)g.W * 4 + 255) / 256 * 256;
+}
+
+int fht_range_adjoint_workspace_size(int w, int h, int S1, int S, int transposed, int t, size_t* bytes)
+{
+    if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
+    if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "adjoint type must be I32 or F32");
+    int64_t r, c;
+    int rc = fht_range_shape(w, h, S1, S, transposed, &r, &c);
+    if (rc) return rc;
+    QuadGeom g = quad_geom(w, h, transposed ? 4 : 1, S1);
+    *bytes = range_adjoint_workspace(g);
+    return FHT_OK;
+}
+
+int fht_range_adjoint(const void* grad, int t, int64_t ld_grad, int S1, int S, int transposed, void* grad_img,
+                      int64_t ld_img, int w, int h, void* workspace, size_t ws_bytes, void* stream)
+{
+    int64_t rows, cols;
+    int rc = fht_range_shape(w, h, S1, S, transposed, &rows, &cols);
+    if (rc) return rc;
+    if (!grad || !grad_img) return fail(FHT_ERR_INVALID, "null gradient pointer");
+    if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "adjoint type must be I32 or F32");
+    if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
+    if (ld_grad < cols) return fail(FHT_ERR_INVALID, "ld_grad %lld < %lld", (long long)ld_grad, (long long)cols);
+    QuadGeom g = quad_geom(w, h, transposed ? 4 : 1, S1);
+    const size_t need = range_adjoint_workspace(g);
+    if (!workspace || ws_bytes < need)
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    unsigned char* ws = (unsigned char*)workspace;
+    unsigned char* a0 = ws + layout_bands(&g, 1, 4, 0);
+    hipStream_t s = (hipStream_t)stream;
+    // passes in reverse order; the one reading the gradient reads rows 0..S,
+    // the last one writes the full-width source gradient a0 (n x W)
+    for (int p = g.npass - 1; p >= 0; --p) {
+        AdjDesc d = make_adj_desc(g, p, grad, ld_grad, nullptr, 0, w, h, ws, 0, 1, -1, 0, 0, 0, 0);
+        if (p == g.npass - 1) d.row_limit = S;
+        if (p == 0) {
+            const int VW = kWinCols - (1 << g.G[0]);
+            d.dst = a0;
+            d.dst_ld = g.W;
+            d.dst_kind = 0;
+            d.dst_off = 0;
+            d.dst_bw = g.W;
+            d.accumulate = 0;
+            d.x_start = 0;
+            d.n_windows = (g.W + VW - 1) / VW;
+        }
+        AdjLaunch L{};
+        L.d[0] = d;
+        L.nd = 1;
+        hipError_t e = g.k <= 2 ? launch_adjoint_direct(L, g.k, t, s) : launch_adjoint_pass(L, t, s);
+        if (e != hipSuccess) return hip_fail(e, "range adjoint pass launch");
+    }
+    hipError_t e = launch_unshear(a0, g.W, g.n, S1, grad_img, ld_img, w, h, transposed, 4, s);
+    if (e != hipSuccess) return hip_fail(e, "range adjoint unshear launch");
     return FHT_OK;
 }
 

@@ -820,7 +820,7 @@ template <typename T>
 __device__ __forceinline__ bool adj_issue_hough(const AdjDesc& d, int s_row, int xrow, int lane, T (&v)[8], int& e0)
 {
     const int W = d.W;
-    const bool skip = s_row == d.skip_row;
+    const bool skip = s_row == d.skip_row || s_row > d.row_limit;
     const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
     const int roll = d.shifted ? ((d.roll_a + d.roll_b * s_row) >> 1) : 0;
     e0 = lane_run_start(xrow, roll, lane, W, d.mirror);
@@ -1106,7 +1106,7 @@ template <typename T, int J, int K>
 __device__ T adj_direct(const AdjDesc& d, int row, int x)
 {
     if constexpr (J == K) {
-        if (row == d.skip_row) return (T)0;
+        if (row == d.skip_row || row > d.row_limit) return (T)0;
         const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * row) * d.src_ld;
         const int roll = d.shifted ? ((d.roll_a + d.roll_b * row) >> 1) : 0;
         return src[mod_pos((long long)x + roll, d.W)];
@@ -1131,13 +1131,32 @@ __global__ __launch_bounds__(256) void fht_adj_direct_kernel(const AdjLaunch L)
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int R = blockIdx.y;
     if (R >= d.n) return;
-    const int cols = d.dst_kind == 1 ? d.img_w : d.img_h;
-    const int rows = d.dst_kind == 1 ? d.img_h : d.img_w;
+    // dst_kind 1: image, 2: transposed image, 0: the full n x W source buffer
+    const int cols = d.dst_kind == 1 ? d.img_w : (d.dst_kind == 2 ? d.img_h : d.W);
+    const int rows = d.dst_kind == 1 ? d.img_h : (d.dst_kind == 2 ? d.img_w : d.n);
     if (x >= cols || R >= rows) return;
     const T v = adj_direct<T, 0, K>(d, R, x);
-    T* p = d.dst_kind == 1 ? reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x
-                           : reinterpret_cast<T*>(d.dst) + (long long)x * d.dst_ld + R;
+    T* p = d.dst_kind == 2 ? reinterpret_cast<T*>(d.dst) + (long long)x * d.dst_ld + R
+                           : reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x;
     *p = d.accumulate ? (T)(*p + v) : v;
+}
+
+// ------------------------------------------------ angle-range adjoint tail
+
+// The gradient of the sheared padded source, a0[r, xi] (n x W), read back
+// as the gradient of the source cell (r, c), xi = c + sigma(r) (section 4),
+// cropped to the image.  One thread per image cell, consecutive x.
+template <typename T>
+__global__ __launch_bounds__(256) void fht_unshear_kernel(const T* a0, int W, int n, int S1, T* img, int64_t ld_img,
+                                                          int w, int h, int transposed)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= w || y >= h) return;
+    const int r = transposed ? x : y;
+    const int c = transposed ? y : x;
+    const int xi = mod_pos((long long)c + shear_of_row(r, S1, n), W);
+    img[(long long)y * ld_img + x] = a0[(long long)r * W + xi];
 }
 
 // ------------------------------------------------------------- fhtshift

@@ -80,6 +80,7 @@ struct AdjDesc {
     int dst_off, dst_bw;
     int x_start, n_windows, n_row_tiles;
     int row_base, row_sign, skip_row;  // Hough source row mapping
+    int row_limit;        // Hough rows (shifts) above it read as zero (angle range: S)
     int shifted, roll_a, roll_b;
 };
 struct AdjLaunch {
@@ -125,6 +126,10 @@ hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s);
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,
                         int hp, int wp, int inverse, hipStream_t s);
+// Angle-range adjoint, last step: img[y, x] = a0[r, (c + sigma(r)) mod W]
+// (r, c) = (y, x), or (x, y) when transposed; a0 is n x W, row pitch W.
+hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,
+                          int transposed, int elem_bytes, hipStream_t s);
 int engine_grid_size();
 
 // Launch timing (fht_timing_enable): the rocprof-style name of a pass kernel

@@ -138,7 +138,7 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
 {
     int cols = 1, n = 1;
     for (int i = 0; i < L.nd; ++i) {
-        const int c = L.d[i].dst_kind == 1 ? L.d[i].img_w : L.d[i].img_h;
+        const int c = L.d[i].dst_kind == 1 ? L.d[i].img_w : (L.d[i].dst_kind == 2 ? L.d[i].img_h : L.d[i].W);
         cols = c > cols ? c : cols;
         n = L.d[i].n > n ? L.d[i].n : n;
     }

@@ -127,6 +127,15 @@ hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem
     return hipGetLastError();
 }
 
+hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,
+                          int transposed, int elem_bytes, hipStream_t s)
+{
+    if (elem_bytes != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fht_unshear_kernel<uint32_t>, dim3((w + 255) / 256, h), dim3(256), 0, s, (const uint32_t*)a0,
+                       W, n, S1, (uint32_t*)img, ld_img, w, h, transposed);
+    return hipGetLastError();
+}
+
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,
                         int hp, int wp, int inverse, hipStream_t s)
 {

@@ -8,8 +8,10 @@ Names follow the C ABI in include/fht.h:
   forward(img, quads='full', shifted=False, op='sum')
                                               sections 3.1, 3.3 (and 5; op='max': section 1)
   range_transform(img, S1, S, transposed)     section 4
+  range_pieces / range_any(img, deg_lo, deg_hi) any inclination range, split into calls
   shift(hough, w, h, inverse)                 section 5 (fhtshift)
   adjoint(grad, w, h, quads, shifted)         transpose of forward
+  range_adjoint(grad, w, h, S1, S, transposed) transpose of range_transform; RangeFunction
   FHTFunction                                 autograd wrapper
   BatchPlan                                   batched forward (graph-capturable)
   timing_enable / timing_report               per-kernel launch times (HIP events)
@@ -61,6 +63,8 @@ SIGNATURES = {
     "fht_batch_forward": (_I, [_P, _P, _P, _P, _SZ, _P]),
     "fht_batch_plan_destroy": (_I, [_P]),
     "fht_pass_split": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "fht_range_adjoint_workspace_size": (_I, [_I, _I, _I, _I, _I, _I, _PSZ]),
+    "fht_range_adjoint": (_I, [_P, _I, _I64, _I, _I, _I, _P, _I64, _I, _I, _P, _SZ, _P]),
     "fht_timing_enable": (_I, [_I]),
     "fht_timing_report": (_I, [_I, ctypes.c_char_p, _I, _PI64, ctypes.POINTER(ctypes.c_double)]),
 }
@@ -231,6 +235,88 @@ def range_transform(img: torch.Tensor, S1: int, S: int, transposed: bool = False
                          out.stride(0), ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "fht_range")
     return out
+
+
+def range_adjoint(grad: torch.Tensor, w: int, h: int, S1: int, S: int, transposed: bool = False,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """Adjoint of range_transform: (S+1) x W gradient -> h x w image gradient."""
+    _check_2d(grad, "grad")
+    t = _acc_code(grad.dtype)
+    rows, cols = range_shape(w, h, S1, S, transposed)
+    if grad.shape[0] != rows or grad.shape[1] != cols:
+        raise ValueError("grad must be %dx%d" % (rows, cols))
+    if out is None:
+        out = torch.empty((h, w), dtype=grad.dtype, device=grad.device)
+    _check_2d(out, "out")
+    b = ctypes.c_size_t()
+    _check(lib().fht_range_adjoint_workspace_size(w, h, S1, S, int(transposed), t, ctypes.byref(b)),
+           "fht_range_adjoint_workspace_size")
+    ws = _workspace(b.value, grad.device)
+    rc = lib().fht_range_adjoint(grad.data_ptr(), t, grad.stride(0), S1, S, int(transposed), out.data_ptr(),
+                                 out.stride(0), w, h, ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, "fht_range_adjoint")
+    return out
+
+
+class RangeFunction(torch.autograd.Function):
+    """Differentiable angle-range transform of a float32 image (section 4)."""
+
+    @staticmethod
+    def forward(ctx, img, S1, S, transposed=False):
+        ctx.shape = tuple(img.shape)
+        ctx.args = (int(S1), int(S), bool(transposed))
+        return range_transform(img.contiguous(), S1, S, transposed)
+
+    @staticmethod
+    def backward(ctx, g):
+        h, w = ctx.shape
+        S1, S, tr = ctx.args
+        return range_adjoint(g.contiguous(), w, h, S1, S, tr), None, None, None
+
+
+def range_pieces(h: int, w: int, deg_lo: float, deg_hi: float):
+    """Split an inclination range [deg_lo, deg_hi] (degrees from the vertical,
+    -90 <= deg_lo <= deg_hi <= 90, positive = x grows with y) into range
+    calls (section 4).  Mostly vertical inclinations |phi| <= 45 run on the
+    image; mostly horizontal ones on the transposed image, where a line of
+    inclination phi has inclination 90 - phi (phi > 45) or -90 - phi
+    (phi < -45).  In each family the integer slope steps k = (n-1) tan(phi)
+    from floor to ceil are cut into chunks of at most n steps (one call
+    computes shifts 0..S <= n-1); chunk [k0, k1] is S1 = -k0, S = k1 - k0, and
+    its row s holds slope (s + k0) / (n - 1).  Returns a list of dicts with
+    keys transposed, n, S1, S, k (= (k0, k1))."""
+    if not (-90.0 <= deg_lo <= deg_hi <= 90.0):
+        raise ValueError("need -90 <= deg_lo <= deg_hi <= 90")
+    pieces = []
+
+    def family(lo, hi, transposed):
+        n = 1 << max(0, (int(w if transposed else h) - 1).bit_length())
+        if n == 1:
+            pieces.append(dict(transposed=transposed, n=1, S1=0, S=0, k=(0, 0)))
+            return
+        k0 = math.floor((n - 1) * math.tan(math.radians(lo)) + 1e-9)
+        k1 = math.ceil((n - 1) * math.tan(math.radians(hi)) - 1e-9)
+        k0, k1 = max(k0, -(n - 1)), min(k1, n - 1)
+        a = k0
+        while a <= k1:
+            b = min(a + n - 1, k1)
+            pieces.append(dict(transposed=transposed, n=n, S1=-a, S=b - a, k=(a, b)))
+            a = b + 1
+
+    if deg_hi >= -45.0 and deg_lo <= 45.0:
+        family(max(deg_lo, -45.0), min(deg_hi, 45.0), False)
+    if deg_hi > 45.0:
+        family(90.0 - deg_hi, 90.0 - max(deg_lo, 45.0), True)
+    if deg_lo < -45.0:
+        family(-90.0 - min(deg_hi, -45.0), -90.0 - deg_lo, True)
+    return pieces
+
+
+def range_any(img: torch.Tensor, deg_lo: float, deg_hi: float):
+    """Angle-range transforms covering [deg_lo, deg_hi]: a list of
+    (piece, Hough image) with the pieces of range_pieces."""
+    h, w = img.shape
+    return [(p, range_transform(img, p["S1"], p["S"], p["transposed"])) for p in range_pieces(h, w, deg_lo, deg_hi)]
 
 
 def range_degrees(img: torch.Tensor, deg_lo: float, deg_hi: float, transposed: bool = False):
