@@ -216,6 +216,34 @@ int fht_batch_forward(const fht_batch_plan* plan, const void* const* imgs, void*
 int fht_batch_plan_destroy(fht_batch_plan* plan);
 
 /*
+ * From a Hough cell back to the image (sections 3.2 and 3.3), host only.
+ * row, x0: a cell of the Hough image of an h x w image with quads = FHT_FULL
+ * (row in 0..2(w'+h')-4, attributed to its quadrant by the row order of
+ * section 3.3) or a single quadrant (row = shift); shifted = 1 if the image
+ * was fhtshift-ed (full image only).  The cell's dyadic pattern is walked row
+ * by row on the padded source with cyclic columns (cases a and b of
+ * section 3.2); seg[0..3] receive the image coordinates (x, y) of its first
+ * and last pixel inside the image and seg[4] the number of such pixels.
+ * seg[4] = 0: the pattern lies in the zero extension only (case c, the black
+ * zone); seg[0..3] are then 0.  Mostly horizontal quadrants (3, 4) give
+ * their pattern along image columns.
+ */
+int fht_cell_segment(int w, int h, unsigned quads, int64_t row, int64_t x0, int shifted, int32_t* seg);
+
+/*
+ * Local maxima of a Hough image (t = FHT_I32 or FHT_F32, rows x cols, pitch
+ * ld, device): cells with value > threshold that are the strict maximum of
+ * their (2 radius + 1)^2 neighbourhood, cyclic in columns and clipped in
+ * rows; equal values are ordered by linear index (row * cols + col), so a
+ * plateau yields one cell.  The linear indices of the first max_out maxima
+ * found are written to out (device, unordered) and *count (device, unsigned)
+ * receives the total number found, which may exceed max_out.  radius in
+ * 1..64 and 2 radius + 1 <= cols.  Asynchronous on stream.
+ */
+int fht_peaks(const void* hough, int t, int64_t rows, int64_t cols, int64_t ld, int radius, double threshold,
+              int64_t* out, int max_out, unsigned* count, void* stream);
+
+/*
  * Launch timing (instrumentation, not part of the method).  fht_timing_enable
  * (1) clears previous records and starts recording: every pass kernel the
  * library enqueues afterwards (forward, range, adjoint and batched passes) is

@@ -14,6 +14,7 @@ Names follow the C ABI in include/fht.h:
   range_adjoint(grad, w, h, S1, S, transposed) transpose of range_transform; RangeFunction
   FHTFunction                                 autograd wrapper
   BatchPlan                                   batched forward (graph-capturable)
+  cell_segment / peaks / detect_lines          Hough cell -> image segment (sections 3.2, 3.3)
   timing_enable / timing_report               per-kernel launch times (HIP events)
 """
 from __future__ import annotations
@@ -65,6 +66,8 @@ SIGNATURES = {
     "fht_pass_split": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "fht_range_adjoint_workspace_size": (_I, [_I, _I, _I, _I, _I, _I, _PSZ]),
     "fht_range_adjoint": (_I, [_P, _I, _I64, _I, _I, _I, _P, _I64, _I, _I, _P, _SZ, _P]),
+    "fht_cell_segment": (_I, [_I, _I, _U, _I64, _I64, _I, _PI32]),
+    "fht_peaks": (_I, [_P, _I, _I64, _I64, _I64, _I, ctypes.c_double, _P, _I, _P, _P]),
     "fht_timing_enable": (_I, [_I]),
     "fht_timing_report": (_I, [_I, ctypes.c_char_p, _I, _PI64, ctypes.POINTER(ctypes.c_double)]),
 }
@@ -389,6 +392,46 @@ class FHTFunction(torch.autograd.Function):
 
 def fht(img, quads="full", shifted=False):
     return FHTFunction.apply(img, quads, shifted)
+
+
+def cell_segment(w: int, h: int, row: int, x0: int, quads="full", shifted: bool = False):
+    """Image segment of Hough cell (row, x0) (sections 3.2, 3.3): ((xa, ya),
+    (xb, yb), pixels) or None in the black zone."""
+    seg = (ctypes.c_int32 * 5)()
+    _check(lib().fht_cell_segment(w, h, _quads(quads), row, x0, int(shifted), seg), "fht_cell_segment")
+    if seg[4] == 0:
+        return None
+    return (seg[0], seg[1]), (seg[2], seg[3]), seg[4]
+
+
+def peaks(hough: torch.Tensor, radius: int = 4, threshold: float = 0.0, max_out: int = 4096):
+    """Local maxima of a Hough image: [(value, row, col)] by decreasing value
+    (ties by index), and the total number found (may exceed max_out)."""
+    _check_2d(hough, "hough")
+    t = _acc_code(hough.dtype)
+    rows, cols = hough.shape
+    out = torch.empty(max_out, dtype=torch.int64, device=hough.device)
+    count = torch.zeros(1, dtype=torch.int32, device=hough.device)
+    _check(lib().fht_peaks(hough.data_ptr(), t, rows, cols, hough.stride(0), radius, float(threshold),
+                           out.data_ptr(), max_out, count.data_ptr(), _stream()), "fht_peaks")
+    total = int(count.item())
+    idx = out[:min(total, max_out)].cpu().tolist()
+    res = []
+    if idx:
+        flat = torch.tensor(idx, dtype=torch.int64, device=hough.device)
+        rr, cc = flat // cols, flat % cols
+        vals = hough[rr, cc].cpu().tolist()
+        res = sorted(((v, i // cols, i % cols) for v, i in zip(vals, idx)), key=lambda e: (-e[0], e[1], e[2]))
+    return res, total
+
+
+def detect_lines(img: torch.Tensor, k: int = 8, radius: int = 4, threshold: float = 0.0):
+    """Full forward, the k strongest local maxima, and their image segments:
+    [(value, row, x0, segment)] (segment as in cell_segment)."""
+    h, w = img.shape
+    H = forward(img)
+    found, _ = peaks(H, radius, threshold)
+    return [(v, r, c, cell_segment(w, h, r, c)) for v, r, c in found[:k]]
 
 
 def timing_enable(on: bool = True):

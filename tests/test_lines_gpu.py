@@ -1,0 +1,94 @@
+"""Peaks of a Hough image on the GPU and the way back to image lines
+(sections 3.2, 3.3).  fht_peaks against a NumPy scan of the same local-max
+rule; detect_lines recovers planted dyadic patterns exactly and planted
+straight lines to within the dyadic deviation."""
+import numpy as np
+import pytest
+import torch
+
+import brute_force as bf
+from gpu_util import dev
+from paper_1811_06378_amd import fht, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _numpy_peaks(H, radius, thr):
+    rows, cols = H.shape
+    idx = np.arange(rows * cols).reshape(rows, cols)
+    ok = H > thr
+    for dr in range(-radius, radius + 1):
+        for dc in range(-radius, radius + 1):
+            if dr == 0 and dc == 0:
+                continue
+            U = np.full_like(H, -np.inf, dtype=np.float64)
+            I = np.full(H.shape, -1, dtype=np.int64)
+            src = slice(max(0, dr), rows + min(0, dr))
+            dst = slice(max(0, -dr), rows + min(0, -dr))
+            U[dst] = np.roll(H, -dc, axis=1)[src]
+            I[dst] = np.roll(idx, -dc, axis=1)[src]
+            ok &= ~((U > H) | ((U == H) & (I < idx) & (I >= 0)))
+    r, c = np.nonzero(ok)
+    return sorted(zip(r.tolist(), c.tolist()))
+
+
+@pytest.mark.parametrize("kind,radius", [("i32", 1), ("i32", 3), ("f32", 2), ("f32", 5)])
+def test_peaks_match_numpy(kind, radius):
+    rng = np.random.default_rng(radius)
+    if kind == "i32":
+        H = rng.integers(0, 20, size=(61, 96)).astype(np.int32)   # many ties
+    else:
+        H = rng.random((61, 96)).astype(np.float32)
+    found, total = fht.peaks(dev(H), radius=radius, threshold=0.5, max_out=100000)
+    assert total == len(found)
+    got = sorted((r, c) for _, r, c in found)
+    assert got == _numpy_peaks(H.astype(np.float64), radius, 0.5)
+    vals = [v for v, _, _ in found]
+    assert vals == sorted(vals, reverse=True)
+
+
+def test_peaks_truncation_reports_total():
+    H = np.zeros((20, 40), dtype=np.int32)
+    H[::4, ::4] = 5
+    found, total = fht.peaks(dev(H), radius=1, threshold=0, max_out=7)
+    assert total == 50 and len(found) == 7
+
+
+def _full_row(q, s, hp, wp):
+    return {1: hp - 1 - s, 2: hp - 1 + s, 3: 2 * hp + wp - 3 - s, 4: 2 * hp + wp - 3 + s}[q]
+
+
+def test_detect_planted_patterns():
+    """Exact dyadic patterns planted in sparse noise come back as the
+    strongest peaks, at their own cells, with their own segments."""
+    h = w = 256
+    img = (np.random.default_rng(1).random((h, w)) < 0.01).astype(np.int32)
+    planted = [(1, 40, 30), (2, 100, 200), (3, 70, 60), (4, 150, 20)]
+    for q, s, x0 in planted:
+        img = np.maximum(img, (bf.pattern_mask(h, w, q, s, x0) > 0).astype(np.int32))
+    found = fht.detect_lines(dev(img.astype(np.float32)), k=4, radius=6)
+    cells = {(r, c) for _, r, c, _ in found}
+    for q, s, x0 in planted:
+        r = _full_row(q, s, 256, 256)
+        assert (r, x0) in cells, (q, s, x0)
+        seg = fht.cell_segment(w, h, r, x0)
+        assert seg is not None and seg[2] == int((bf.pattern_mask(h, w, q, s, x0) > 0).sum())
+
+
+def test_detect_rasterized_lines():
+    """Straight lines x = round(x0 + t y) over all rows: the recovered
+    segments end within 2 pixels of the line's ends (the dyadic deviation at
+    n = 256 is 4/3)."""
+    h = w = 256
+    rng = np.random.default_rng(7)
+    img = (rng.random((h, w)) < 0.02).astype(np.float32)
+    lines = [(20.0, 0.25), (90.0, 0.55), (160.0, 0.3)]
+    ys = np.arange(h)
+    for x0, t in lines:
+        img[ys, np.rint(x0 + t * ys).astype(int)] = 1.0
+    found = fht.detect_lines(dev(img), k=3, radius=8)
+    segs = [seg for _, _, _, seg in found]
+    for x0, t in lines:
+        ok = [s for s in segs if s and abs(s[0][0] - x0) <= 2 and s[0][1] == 0
+              and abs(s[1][0] - (x0 + t * (h - 1))) <= 2 and s[1][1] == h - 1]
+        assert ok, (x0, t, segs)
