@@ -27,4 +27,6 @@ from .oracle import (  # noqa: F401
     quadrant_op,
     full_op,
     range_adjoint,
+    range_scaled,
+    scaled_sizes,
 )

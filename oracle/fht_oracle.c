@@ -334,6 +334,35 @@ int oracle_range(const double* img, int64_t w, int64_t h, int64_t ld, int64_t S1
 }
 
 /*
+ * Angle range of the image scaled along the axis the range shears (image
+ * columns; image rows when transposed) by alpha = num/den (section 4: a
+ * scale maps [-arctg(1/alpha); 0] onto [-45; 0], done in the first
+ * iteration).  The paper fixes no resampling rule; this reading takes the
+ * nearest source sample: the scaled image has ceil(alpha * extent) samples
+ * along that axis and sample x is source sample floor(x * den / num).  The
+ * scaled image is built explicitly, then transformed by oracle_range.
+ * out: (S+1) x W_alpha with W_alpha from the scaled sizes.
+ */
+int oracle_range_scaled(const double* img, int64_t w, int64_t h, int64_t ld, int64_t num, int64_t den,
+                        int64_t S1, int64_t S, int transposed, int single, double* out)
+{
+    if (!img || !out || w < 1 || h < 1 || ld < w || num < 1 || den < 1) return ORACLE_BAD_ARG;
+    int64_t ws = transposed ? w : (w * num + den - 1) / den;
+    int64_t hs = transposed ? (h * num + den - 1) / den : h;
+    double* sc = (double*)malloc(sizeof(double) * (size_t)(ws * hs));
+    if (!sc) return ORACLE_NO_MEMORY;
+    for (int64_t y = 0; y < hs; ++y)
+        for (int64_t x = 0; x < ws; ++x) {
+            int64_t sy = transposed ? (y * den) / num : y;
+            int64_t sx = transposed ? x : (x * den) / num;
+            sc[y * ws + x] = img[sy * ld + sx];
+        }
+    int rc = oracle_range(sc, ws, hs, ws, S1, S, transposed, single, out);
+    free(sc);
+    return rc;
+}
+
+/*
  * One Hough cell by its definition: the sum of the padded source along one
  * dyadic pattern, H_q[s, x] = sum_r src[r, (x + dir*D_n(s, r)) mod W].
  * Used for sampled checks at sizes where the full oracle is too slow.

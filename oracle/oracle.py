@@ -60,6 +60,9 @@ def _load():
             lib.oracle_range_adjoint.restype = ctypes.c_int
             lib.oracle_range_adjoint.argtypes = [_PD, _I64, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD,
                                                  _I64]
+            lib.oracle_range_scaled.restype = ctypes.c_int
+            lib.oracle_range_scaled.argtypes = [_PD, _I64, _I64, _I64, _I64, _I64, _I64, _I64, ctypes.c_int,
+                                                ctypes.c_int, _PD]
             lib.oracle_quadrant_op.restype = ctypes.c_int
             lib.oracle_quadrant_op.argtypes = [_PD, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _PD]
             lib.oracle_full_op.restype = ctypes.c_int
@@ -168,6 +171,26 @@ def range_adjoint(g, w: int, h: int, S1: int, S: int, transposed: bool = False, 
     a = _as_f64(g)
     out = np.empty((h, w), dtype=np.float64)
     _rc(_load().oracle_range_adjoint(_ptr(a), w, h, S1, S, int(transposed), int(single), _ptr(out), w))
+    return out
+
+
+def scaled_sizes(w: int, h: int, num: int, den: int, transposed: bool = False):
+    """Image sizes after scaling the sheared axis by num/den (ceil)."""
+    if transposed:
+        return w, -(-h * num // den)
+    return -(-w * num // den), h
+
+
+def range_scaled(img, num: int, den: int, S1: int, S: int, transposed: bool = False,
+                 single: bool = False) -> np.ndarray:
+    """Angle range of the image scaled by num/den along the sheared axis
+    (section 4), nearest-sample reading: (S+1) x W of the scaled sizes."""
+    a = _as_f64(img)
+    h, w = a.shape
+    ws, hs = scaled_sizes(w, h, num, den, transposed)
+    W = next_pow2(ws) + next_pow2(hs)
+    out = np.empty((S + 1, W), dtype=np.float64)
+    _rc(_load().oracle_range_scaled(_ptr(a), w, h, w, num, den, S1, S, int(transposed), int(single), _ptr(out)))
     return out
 
 

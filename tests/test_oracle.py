@@ -443,3 +443,44 @@ def test_range_adjoint_unsheared_full_range_is_the_quadrant_adjoint(oracle_mod):
     g4 = rng.integers(-9, 10, size=(16, 32)).astype(np.float64)
     np.testing.assert_array_equal(oracle_mod.range_adjoint(g4, w, h, 0, 15, True),
                                   oracle_mod.adjoint_quadrant(g4, w, h, 4))
+
+
+# ---- scale along the sheared axis in the first iteration (section 4);
+# the nearest-sample resampling is this build's reading (the paper fixes none)
+
+@pytest.mark.parametrize("tr", [False, True])
+def test_scale_one_is_the_plain_range(oracle_mod, tr):
+    img = _rand(12, 9, seed=1)
+    np.testing.assert_array_equal(oracle_mod.range_scaled(img, 3, 3, 2, 5, tr), oracle_mod.range_transform(img, 2, 5, tr))
+
+
+def test_scale_two_duplicates_columns(oracle_mod):
+    img = _rand(10, 7, seed=2)
+    np.testing.assert_array_equal(oracle_mod.range_scaled(img, 2, 1, 3, 6),
+                                  oracle_mod.range_transform(np.repeat(img, 2, axis=1), 3, 6))
+
+
+def test_scale_half_keeps_every_other_column(oracle_mod):
+    img = _rand(10, 16, seed=3)
+    np.testing.assert_array_equal(oracle_mod.range_scaled(img, 1, 2, -2, 7),
+                                  oracle_mod.range_transform(img[:, ::2], -2, 7))
+
+
+def test_scale_transposed_scales_rows(oracle_mod):
+    img = _rand(6, 11, seed=4)
+    np.testing.assert_array_equal(oracle_mod.range_scaled(img, 3, 1, 1, 7, True),
+                                  oracle_mod.range_transform(np.repeat(img, 3, axis=0), 1, 7, True))
+
+
+def test_scale_maps_inclination_by_the_tangent(oracle_mod):
+    """A line of slope t = tan(beta) peaks, after scaling by alpha, at the
+    shift of slope alpha * t (section 4: beta' = arctg(alpha tg beta)),
+    to within the dyadic deviation."""
+    n = 256
+    for alpha_num, alpha_den, t in [(2, 1, 0.3), (2, 1, 0.45), (3, 2, 0.5), (1, 2, 0.9)]:
+        img = np.zeros((n, n))
+        ys = np.arange(n)
+        img[ys, np.rint(20 + t * ys).astype(int)] = 1.0
+        R = oracle_mod.range_scaled(img, alpha_num, alpha_den, 0, n - 1)
+        s_peak = int(np.unravel_index(np.argmax(R), R.shape)[0])
+        assert abs(s_peak - (alpha_num / alpha_den) * t * (n - 1)) <= 4.0, (alpha_num, alpha_den, t, s_peak)
