@@ -168,6 +168,25 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 void* stream);
 
 /*
+ * Angle range of the image scaled along the sheared axis by alpha = num/den
+ * (section 4: a scale in the first iteration maps [-arctg(1/alpha); 0] onto
+ * [-45; 0], and the shear then selects the range).  The paper fixes no
+ * resampling rule; here the scaled image has ceil(alpha * w) columns (rows
+ * when transposed) and sample x is the source sample floor(x * den / num)
+ * (nearest sample; alpha > 1 repeats samples, alpha < 1 skips them).  The
+ * result is fht_range of that scaled image: shape and workspace from the
+ * two helpers below, which take the unscaled w, h.  num, den in 1..64.
+ * img is the unscaled h x w image; everything else as fht_range.
+ */
+int fht_range_scaled_shape(int w, int h, int num, int den, int S1, int S, int transposed, int64_t* rows,
+                           int64_t* cols);
+int fht_range_scaled_workspace_size(int w, int h, int num, int den, int S1, int S, int transposed, int in_t,
+                                    int acc_t, size_t* bytes);
+int fht_range_scaled(const void* img, int in_t, int w, int h, int64_t ld_img, int num, int den, int S1, int S,
+                     int transposed, void* hough, int acc_t, int64_t ld_hough, void* workspace, size_t ws_bytes,
+                     void* stream);
+
+/*
  * Adjoint of fht_range (transpose of the angle-range transform of section 4):
  * the gradient of rows 0..S goes back through the transposed stages to the
  * padded source sheared by sigma(y), is read back at the unsheared columns,

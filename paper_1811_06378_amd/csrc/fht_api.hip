@@ -557,6 +557,77 @@ int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, i
     return run_forward(&g, descs, 1, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream);
 }
 
+// Scaled angle range (section 4): the scaled image has ceil(extent * num /
+// den) samples along the sheared axis (columns; rows when transposed).
+static int scaled_sizes(int w, int h, int num, int den, int transposed, int* ws, int* hs)
+{
+    if (num < 1 || den < 1 || num > 64 || den > 64)
+        return fail(FHT_ERR_INVALID, "scale %d/%d: numerator and denominator in 1..64", num, den);
+    const int64_t a = transposed ? h : w;
+    const int64_t sc = (a * num + den - 1) / den;
+    if (sc > FHT_MAX_SIDE) return fail(FHT_ERR_UNSUPPORTED, "scaled side %lld exceeds %d", (long long)sc, FHT_MAX_SIDE);
+    *ws = transposed ? w : (int)sc;
+    *hs = transposed ? (int)sc : h;
+    return FHT_OK;
+}
+
+int fht_range_scaled_shape(int w, int h, int num, int den, int S1, int S, int transposed, int64_t* rows,
+                           int64_t* cols)
+{
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    int ws, hs;
+    rc = scaled_sizes(w, h, num, den, transposed, &ws, &hs);
+    if (rc) return rc;
+    return fht_range_shape(ws, hs, S1, S, transposed, rows, cols);
+}
+
+int fht_range_scaled_workspace_size(int w, int h, int num, int den, int S1, int S, int transposed, int in_t,
+                                    int acc_t, size_t* bytes)
+{
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    int ws, hs;
+    rc = scaled_sizes(w, h, num, den, transposed, &ws, &hs);
+    if (rc) return rc;
+    return fht_range_workspace_size(ws, hs, S1, S, transposed, in_t, acc_t, bytes);
+}
+
+int fht_range_scaled(const void* img, int in_t, int w, int h, int64_t ld_img, int num, int den, int S1, int S,
+                     int transposed, void* hough, int acc_t, int64_t ld_hough, void* workspace, size_t ws_bytes,
+                     void* stream)
+{
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    int ws, hs;
+    rc = scaled_sizes(w, h, num, den, transposed, &ws, &hs);
+    if (rc) return rc;
+    int64_t rows, cols;
+    rc = fht_range_shape(ws, hs, S1, S, transposed, &rows, &cols);
+    if (rc) return rc;
+    if (!img || !hough) return fail(FHT_ERR_INVALID, "null image or Hough pointer");
+    if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    if (ld_img < w) return fail(FHT_ERR_INVALID, "ld_img %lld < w %d", (long long)ld_img, w);
+    if (ld_hough < cols) return fail(FHT_ERR_INVALID, "ld_hough %lld < %lld", (long long)ld_hough, (long long)cols);
+    QuadGeom g = quad_geom(ws, hs, transposed ? 4 : 1, S1);
+    const size_t need = forward_workspace(&g, 1, acc_t);
+    if (!workspace || ws_bytes < need)
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    PassDesc descs[1][4];
+    for (int p = 0; p < g.npass; ++p) {
+        // the descriptors see the scaled extents; the first pass maps a
+        // scaled sample back to its source sample
+        descs[0][p] = make_pass_desc(g, p, img, ws, hs, ld_img, hough, ld_hough, (unsigned char*)workspace, S1, S, 0,
+                                     1, -1, 0, 0, 0);
+        if (p == 0 && num != den) {
+            descs[0][p].scale_num = num;
+            descs[0][p].scale_den = den;
+        }
+    }
+    return run_forward(&g, descs, 1, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream);
+}
+
 int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, int w, int h, int inverse, void* stream)
 {
     int rc = check_sides(w, h);

@@ -406,6 +406,9 @@ __device__ __forceinline__ bool issue_image_row(const PassDesc& d, int R, int xr
     return !fast && !zero;
 }
 
+// Element loads of one source row.  With a scale (section 4), column e of
+// the scaled image (extent img_w or img_h along the sheared axis) is source
+// sample floor(e * den / num).
 template <typename TIn, typename T>
 __device__ __forceinline__ void patch_image_row(const PassDesc& d, int R, int e0, T (&v)[8])
 {
@@ -413,14 +416,16 @@ __device__ __forceinline__ void patch_image_row(const PassDesc& d, int R, int e0
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int e = run_col(e0, c, d.W, d.mirror);
+        const int es = d.scale_num ? (int)(((long long)e * d.scale_den) / d.scale_num) : e;
         if (d.src_kind == SRC_IMAGE)
-            v[c] = (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + e]) : (T)0;
+            v[c] = (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + es]) : (T)0;
         else
-            v[c] = (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)e * d.src_ld + R]) : (T)0;
+            v[c] = (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)es * d.src_ld + R]) : (T)0;
     }
 }
 
-// Transposed image with a shear: element loads only.
+// Element-load rows (transposed image with a shear, or a scaled source):
+// zeros now, every element loaded by patch_image_row.
 template <typename TIn, typename T>
 __device__ __forceinline__ bool issue_image_t_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
 {
@@ -609,7 +614,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         if (!active) {
 #pragma unroll
             for (int r = 0; r < 8; ++r) zero8(a[r]);
-        } else if (FIRST && d.src_kind == SRC_IMAGE_T && d.S1 == 0) {
+        } else if (FIRST && d.src_kind == SRC_IMAGE_T && d.S1 == 0 && d.scale_num == 0) {
             // first pass (u = 0): the wave's rows are 8 consecutive image columns
             load_rows_transposed<TIn, T>(d, (B << G) + (tr0 & ((1 << G) - 1)), xi0, lane, a);
         } else {
@@ -622,8 +627,10 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                 const int m = (tr0 + r) & ((1 << G) - 1);
                 const int R = (B << (j0 + G)) + (m << j0) + u;
                 if constexpr (FIRST) {
-                    patch[r] = d.src_kind == SRC_IMAGE ? issue_image_row<TIn, T>(d, R, xi0, lane, a[r], e0[r])
-                                                       : issue_image_t_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
+                    // scaled sources take the element path
+                    patch[r] = (d.src_kind == SRC_IMAGE && d.scale_num == 0)
+                                   ? issue_image_row<TIn, T>(d, R, xi0, lane, a[r], e0[r])
+                                   : issue_image_t_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
                 } else {
                     patch[r] = issue_band_row<T>(band + (long long)R * d.src_ld, d.src_off, d.src_bw, d.W,
                                                  xi0 + u * m, lane, a[r], e0[r]);
@@ -1064,10 +1071,11 @@ __device__ __forceinline__ T src_value(const PassDesc& d, int R, int x)
 {
     const int W = d.W;
     const int e = mod_pos((long long)x - shear_of_row(R, d.S1, d.n), W);
+    const int es = d.scale_num ? (int)(((long long)e * d.scale_den) / d.scale_num) : e;
     const TIn* img = reinterpret_cast<const TIn*>(d.src);
     if (d.src_kind == SRC_IMAGE)
-        return (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + e]) : (T)0;
-    return (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)e * d.src_ld + R]) : (T)0;
+        return (R < d.img_h && e < d.img_w) ? to_acc<T>(img[(long long)R * d.src_ld + es]) : (T)0;
+    return (R < d.img_w && e < d.img_h) ? to_acc<T>(img[(long long)es * d.src_ld + R]) : (T)0;
 }
 
 // The same add tree as K stages of the recurrence, evaluated top-down in x

@@ -9,6 +9,7 @@ Names follow the C ABI in include/fht.h:
                                               sections 3.1, 3.3 (and 5; op='max': section 1)
   range_transform(img, S1, S, transposed)     section 4
   range_pieces / range_any(img, deg_lo, deg_hi) any inclination range, split into calls
+  range_scaled(img, num, den, S1, S)          section 4 scale along the sheared axis
   shift(hough, w, h, inverse)                 section 5 (fhtshift)
   adjoint(grad, w, h, quads, shifted)         transpose of forward
   range_adjoint(grad, w, h, S1, S, transposed) transpose of range_transform; RangeFunction
@@ -64,6 +65,9 @@ SIGNATURES = {
     "fht_batch_forward": (_I, [_P, _P, _P, _P, _SZ, _P]),
     "fht_batch_plan_destroy": (_I, [_P]),
     "fht_pass_split": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "fht_range_scaled_shape": (_I, [_I, _I, _I, _I, _I, _I, _I, _PI64, _PI64]),
+    "fht_range_scaled_workspace_size": (_I, [_I, _I, _I, _I, _I, _I, _I, _I, _I, _PSZ]),
+    "fht_range_scaled": (_I, [_P, _I, _I, _I, _I64, _I, _I, _I, _I, _I, _P, _I, _I64, _P, _SZ, _P]),
     "fht_range_adjoint_workspace_size": (_I, [_I, _I, _I, _I, _I, _I, _PSZ]),
     "fht_range_adjoint": (_I, [_P, _I, _I64, _I, _I, _I, _P, _I64, _I, _I, _P, _SZ, _P]),
     "fht_cell_segment": (_I, [_I, _I, _U, _I64, _I64, _I, _PI32]),
@@ -237,6 +241,29 @@ def range_transform(img: torch.Tensor, S1: int, S: int, transposed: bool = False
     rc = lib().fht_range(img.data_ptr(), it, w, h, img.stride(0), S1, S, int(transposed), out.data_ptr(), at,
                          out.stride(0), ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "fht_range")
+    return out
+
+
+def range_scaled(img: torch.Tensor, num: int, den: int, S1: int, S: int, transposed: bool = False,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Angle range (section 4) of the image scaled by num/den along the
+    sheared axis, nearest source sample (see include/fht.h)."""
+    _check_2d(img, "img")
+    h, w = img.shape
+    it, at, odt = _dtypes(img.dtype)
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fht_range_scaled_shape(w, h, num, den, S1, S, int(transposed), ctypes.byref(r), ctypes.byref(c)),
+           "fht_range_scaled_shape")
+    if out is None:
+        out = torch.empty((r.value, c.value), dtype=odt, device=img.device)
+    _check_2d(out, "out")
+    b = ctypes.c_size_t()
+    _check(lib().fht_range_scaled_workspace_size(w, h, num, den, S1, S, int(transposed), it, at, ctypes.byref(b)),
+           "fht_range_scaled_workspace_size")
+    ws = _workspace(b.value, img.device)
+    rc = lib().fht_range_scaled(img.data_ptr(), it, w, h, img.stride(0), num, den, S1, S, int(transposed),
+                                out.data_ptr(), at, out.stride(0), ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, "fht_range_scaled")
     return out
 
 

@@ -143,3 +143,16 @@ def test_batch_plan_host_side():
     assert L.fht_batch_plan_create(ws, hs, 2, 15, 2, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
                                    None) == fht.FHT_ERR_INVALID
     assert L.fht_batch_plan_destroy(None) == 0
+
+
+def test_range_scaled_shape_and_validation():
+    L = fht.lib()
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    # 100 columns scaled by 3/2 -> 150 -> w' = 256; h' = 64
+    assert L.fht_range_scaled_shape(100, 64, 3, 2, 5, 40, 0, ctypes.byref(r), ctypes.byref(c)) == 0
+    assert (r.value, c.value) == (41, 256 + 64)
+    # transposed: the rows are scaled: 64 -> 32 rows -> h' = 32, n = w' = 128
+    assert L.fht_range_scaled_shape(100, 64, 1, 2, 5, 40, 1, ctypes.byref(r), ctypes.byref(c)) == 0
+    assert (r.value, c.value) == (41, 128 + 32)
+    assert L.fht_range_scaled_shape(100, 64, 0, 2, 5, 40, 0, ctypes.byref(r), ctypes.byref(c)) == fht.FHT_ERR_INVALID
+    assert L.fht_range_scaled_shape(100, 64, 65, 1, 5, 40, 0, ctypes.byref(r), ctypes.byref(c)) == fht.FHT_ERR_INVALID

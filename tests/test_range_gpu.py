@@ -88,3 +88,18 @@ def test_range_any_pieces(h, w, lo, hi):
     for p, H in outs:
         want = oracle.range_transform(img.astype(np.float64), p["S1"], p["S"], transposed=p["transposed"])
         assert_equal(host(H).astype(np.float64), want, "range_any piece %s" % (p,))
+
+
+# scaled range (section 4 scale in the first iteration; nearest-sample reading)
+SCALED = [(64, 64, 2, 1, 0, 63, False), (64, 64, 1, 2, 5, 40, False), (100, 70, 3, 2, -10, 90, False),
+          (33, 130, 2, 3, 20, 60, False), (37, 50, 5, 1, 0, 63, True), (120, 90, 1, 3, -7, 20, True),
+          (256, 256, 2, 1, 0, 255, False), (4, 4, 2, 1, 1, 3, False), (3, 9, 1, 2, 0, 3, False)]
+
+
+@pytest.mark.parametrize("h,w,num,den,S1,S,tr", SCALED)
+@pytest.mark.parametrize("kind", ["u8", "f32"])
+def test_range_scaled(h, w, num, den, S1, S, tr, kind):
+    img = synth.random_image(h, w, kind, seed=30 + num)
+    got = host(fht.range_scaled(dev(img), num, den, S1, S, tr))
+    want = oracle.range_scaled(img.astype(np.float64), num, den, S1, S, tr, single=(kind == "f32"))
+    assert_equal(got.astype(np.float64), want, "range scaled %dx%d %d/%d S1=%d S=%d tr=%d" % (h, w, num, den, S1, S, tr))
