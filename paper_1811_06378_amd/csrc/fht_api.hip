@@ -475,6 +475,18 @@ int fht_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, size_t
     return FHT_OK;
 }
 
+// Adjoint workspace: the bands, then one h x w scratch image (row pitch w)
+// per selected quadrant after the first: the image passes of all quadrants
+// run together, each writing its own image, and a final kernel sums them
+// into the gradient in quadrant order.
+static size_t scratch_image_bytes(int w, int h) { return ((size_t)w * (size_t)h * 4 + 255) / 256 * 256; }
+
+static size_t adjoint_workspace(QuadGeom* gs, const int* qs, int nq, int w, int h)
+{
+    (void)qs;
+    return layout_bands(gs, nq, 4, 0) + (size_t)(nq > 1 ? nq - 1 : 0) * scratch_image_bytes(w, h);
+}
+
 int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* bytes)
 {
     if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
@@ -486,7 +498,7 @@ int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* byte
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    *bytes = layout_bands(gs, nq, 4, 0);
+    *bytes = adjoint_workspace(gs, qs, nq, w, h);
     return FHT_OK;
 }
 
@@ -729,18 +741,36 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    const size_t need = layout_bands(gs, nq, 4, 0);
+    const size_t need = adjoint_workspace(gs, qs, nq, w, h);
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     if (workspace && ((uintptr_t)workspace & 255)) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    // image targets: the first quadrant writes grad_img, every later one its
+    // own scratch image; the scratch images are added to grad_img at the end
+    // in quadrant order, so the sum is ((q1 + q2) + q3) + q4
+    unsigned char* scratch = (unsigned char*)workspace + layout_bands(gs, nq, 4, 0);
+    void* target[4];
+    int64_t target_ld[4];
+    int n_scratch = 0;
+    const void* scratch_list[3];
+    for (int i = 0; i < nq; ++i) {
+        target[i] = grad_img;
+        target_ld[i] = ld_img;
+        if (i > 0) {
+            target[i] = scratch;
+            target_ld[i] = w;
+            scratch_list[n_scratch++] = scratch;
+            scratch += scratch_image_bytes(w, h);
+        }
+    }
     AdjDesc descs[4][4];
     for (int i = 0; i < nq; ++i) {
         int base, sign, skip, ra, rb;
         placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
         for (int p = 0; p < gs[i].npass; ++p)
-            descs[i][p] = make_adj_desc(gs[i], p, grad_hough, ld_hough, grad_img, ld_img, w, h,
+            descs[i][p] = make_adj_desc(gs[i], p, grad_hough, ld_hough, target[i], target_ld[i], w, h,
                                         (unsigned char*)workspace, base, sign, skip,
-                                        (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, i > 0 ? 1 : 0);
+                                        (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
     }
     hipStream_t s = (hipStream_t)stream;
     int maxp = 0;
@@ -762,12 +792,30 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 }
             }
         } else {
+            // image passes of every quadrant (distinct targets): tiled ones
+            // grouped by depth, tiny ones by the direct kernel; then the sum
+            for (int G = 3; G <= kMaxG; ++G) {
+                for (int first = 0; first < 2; ++first) {
+                    AdjLaunch L{};
+                    for (int i = 0; i < nq; ++i)
+                        if (gs[i].k > 2 && gs[i].G[0] == G && (gs[i].npass == 1) == (first == 1))
+                            L.d[L.nd++] = descs[i][0];
+                    if (L.nd == 0) continue;
+                    hipError_t e = launch_adjoint_pass(L, t, s);
+                    if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+                }
+            }
             for (int i = 0; i < nq; ++i) {
+                if (gs[i].k > 2) continue;
                 AdjLaunch L{};
                 L.d[0] = descs[i][0];
                 L.nd = 1;
-                hipError_t e = gs[i].k <= 2 ? launch_adjoint_direct(L, gs[i].k, t, s) : launch_adjoint_pass(L, t, s);
+                hipError_t e = launch_adjoint_direct(L, gs[i].k, t, s);
                 if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+            }
+            if (n_scratch > 0) {
+                hipError_t e = launch_sum_images(grad_img, ld_img, scratch_list, n_scratch, w, h, t, s);
+                if (e != hipSuccess) return hip_fail(e, "adjoint sum launch");
             }
         }
     }

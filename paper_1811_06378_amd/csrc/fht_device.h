@@ -1149,6 +1149,38 @@ __global__ __launch_bounds__(256) void fht_adj_direct_kernel(const AdjLaunch L)
     *p = d.accumulate ? (T)(*p + v) : v;
 }
 
+// ------------------------------------------------ adjoint quadrant sum
+
+// The adjoint's per-quadrant images added in quadrant order (consecutive x
+// per thread, four at a time when rows are 16-byte aligned):
+// img = ((img + s0) + s1) + s2.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void fht_sum_images_kernel(T* img, int64_t ld_img, const T* s0, const T* s1,
+                                                             const T* s2, int n, int w, int h)
+{
+    constexpr int V = VEC ? 4 : 1;
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) * V;
+    if (x >= w) return;
+    for (int y = blockIdx.y; y < h; y += gridDim.y) {  // grid y capped at 65535
+        const int64_t i = (int64_t)y * w + x;
+        T* p = img + (int64_t)y * ld_img + x;
+        if constexpr (VEC) {
+            typedef typename vec4u<T>::type V4;
+            V4 v = *reinterpret_cast<const V4*>(p);
+            v = v + *reinterpret_cast<const V4*>(s0 + i);
+            if (n > 1) v = v + *reinterpret_cast<const V4*>(s1 + i);
+            if (n > 2) v = v + *reinterpret_cast<const V4*>(s2 + i);
+            *reinterpret_cast<V4*>(p) = v;
+        } else {
+            T v = *p;
+            v = v + s0[i];
+            if (n > 1) v = v + s1[i];
+            if (n > 2) v = v + s2[i];
+            *p = v;
+        }
+    }
+}
+
 // ------------------------------------------------ angle-range adjoint tail
 
 // The gradient of the sheared padded source, a0[r, xi] (n x W), read back
@@ -1159,12 +1191,13 @@ __global__ __launch_bounds__(256) void fht_unshear_kernel(const T* a0, int W, in
                                                           int w, int h, int transposed)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= w || y >= h) return;
-    const int r = transposed ? x : y;
-    const int c = transposed ? y : x;
-    const int xi = mod_pos((long long)c + shear_of_row(r, S1, n), W);
-    img[(long long)y * ld_img + x] = a0[(long long)r * W + xi];
+    if (x >= w) return;
+    for (int y = blockIdx.y; y < h; y += gridDim.y) {  // grid y capped at 65535
+        const int r = transposed ? x : y;
+        const int c = transposed ? y : x;
+        const int xi = mod_pos((long long)c + shear_of_row(r, S1, n), W);
+        img[(long long)y * ld_img + x] = a0[(long long)r * W + xi];
+    }
 }
 
 // ------------------------------------------------------------- fhtshift
@@ -1203,14 +1236,17 @@ __global__ __launch_bounds__(256) void fht_shift_kernel(const T* in, int64_t ld_
                                                         int hp, int wp, int inverse)
 {
     const int W = hp + wp;
-    const int r = blockIdx.y;
+    const int rows = 2 * (hp + wp) - 3;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= W) return;
-    int roll = row_roll(r, hp, wp) % W;
-    if (inverse) roll = (W - roll) % W;
-    int src = x - roll;
-    if (src < 0) src += W;
-    out[(long long)r * ld_out + x] = in[(long long)r * ld_in + src];
+    // grid y is capped (65535); rows beyond it are taken in strides
+    for (int r = blockIdx.y; r < rows; r += gridDim.y) {
+        int roll = row_roll(r, hp, wp) % W;
+        if (inverse) roll = (W - roll) % W;
+        int src = x - roll;
+        if (src < 0) src += W;
+        out[(long long)r * ld_out + x] = in[(long long)r * ld_in + src];
+    }
 }
 
 }  // namespace fht

@@ -128,6 +128,10 @@ hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s);
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,
                         int hp, int wp, int inverse, hipStream_t s);
+// img[y, x] = ((img + s[0]) + s[1]) + ... over n (1..3) scratch images of
+// h x w, row pitch w; t = 1 (int32) or 2 (float32).
+hipError_t launch_sum_images(void* img, int64_t ld_img, const void* const* scr, int n, int w, int h, int t,
+                             hipStream_t s);
 // Angle-range adjoint, last step: img[y, x] = a0[r, (c + sigma(r)) mod W]
 // (r, c) = (y, x), or (x, y) when transposed; a0 is n x W, row pitch W.
 hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,

@@ -127,12 +127,38 @@ hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem
     return hipGetLastError();
 }
 
+template <typename T>
+static void launch_sum_t(T* img, int64_t ld_img, const void* const* scr, int n, int w, int h, hipStream_t s)
+{
+    const T* a = (const T*)scr[0];
+    const T* b = (const T*)scr[n > 1 ? 1 : 0];
+    const T* c = (const T*)scr[n > 2 ? 2 : 0];
+    const bool vec = (w % 4 == 0) && (ld_img % 4 == 0) && (((uintptr_t)img & 15) == 0);
+    const int gy = h < 65535 ? h : 65535;
+    if (vec)
+        hipLaunchKernelGGL((fht_sum_images_kernel<T, true>), dim3((w / 4 + 255) / 256, gy), dim3(256), 0, s, img, ld_img,
+                           a, b, c, n, w, h);
+    else
+        hipLaunchKernelGGL((fht_sum_images_kernel<T, false>), dim3((w + 255) / 256, gy), dim3(256), 0, s, img, ld_img,
+                           a, b, c, n, w, h);
+}
+
+hipError_t launch_sum_images(void* img, int64_t ld_img, const void* const* scr, int n, int w, int h, int t,
+                             hipStream_t s)
+{
+    if (n < 1 || n > 3) return hipErrorInvalidValue;
+    if (t == 2) launch_sum_t<float>((float*)img, ld_img, scr, n, w, h, s);
+    else if (t == 1) launch_sum_t<int>((int*)img, ld_img, scr, n, w, h, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,
                           int transposed, int elem_bytes, hipStream_t s)
 {
     if (elem_bytes != 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fht_unshear_kernel<uint32_t>, dim3((w + 255) / 256, h), dim3(256), 0, s, (const uint32_t*)a0,
-                       W, n, S1, (uint32_t*)img, ld_img, w, h, transposed);
+    hipLaunchKernelGGL(fht_unshear_kernel<uint32_t>, dim3((w + 255) / 256, h < 65535 ? h : 65535), dim3(256), 0, s,
+                       (const uint32_t*)a0, W, n, S1, (uint32_t*)img, ld_img, w, h, transposed);
     return hipGetLastError();
 }
 
@@ -154,7 +180,7 @@ hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out
         hipLaunchKernelGGL(fht_shift_inplace_kernel<uint32_t>, dim3(rows), dim3(1024), lds_bytes, s,
                            (uint32_t*)out, ld_out, hp, wp, inverse);
     } else {
-        hipLaunchKernelGGL(fht_shift_kernel<uint32_t>, dim3((W + 255) / 256, rows), dim3(256), 0, s,
+        hipLaunchKernelGGL(fht_shift_kernel<uint32_t>, dim3((W + 255) / 256, rows < 65535 ? rows : 65535), dim3(256), 0, s,
                            (const uint32_t*)in, ld_in, (uint32_t*)out, ld_out, hp, wp, inverse);
     }
     return hipGetLastError();
