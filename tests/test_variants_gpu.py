@@ -1,0 +1,38 @@
+"""The opt-in launch variants (read once per process from the environment):
+FHT_ENGINE=1, the persistent queue engine, and FHT_NT=1, streaming stores
+of the Hough image.  Each runs in one child process that checks a few
+forward transforms against the oracle and prints OK."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CHILD = r"""
+import sys
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+import numpy as np, torch
+import oracle
+from paper_1811_06378_amd import fht, synth
+for (h, w, kind) in [(5, 13, "u8"), (129, 257, "u8"), (300, 520, "f32"), (1000, 70, "i32")]:
+    img = synth.random_image(h, w, kind, seed=3)
+    got = fht.forward(torch.from_numpy(img).cuda()).cpu().numpy().astype(np.float64)
+    want = oracle.full(img.astype(np.float64), single=(kind == "f32"))
+    assert np.array_equal(got, want), (h, w, kind)
+img = synth.random_image(100, 37, "u8", seed=4)
+got = fht.forward(torch.from_numpy(img).cuda(), quads=[2, 3]).cpu().numpy().astype(np.float64)
+assert np.array_equal(got, oracle.stacked_quadrants(img, [2, 3]))
+print("OK")
+"""
+
+
+@pytest.mark.parametrize("env", [{"FHT_ENGINE": "1"}, {"FHT_NT": "1"}])
+def test_variant_matches_oracle(env):
+    code = CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"))
+    r = subprocess.run([sys.executable, "-c", code], env={**os.environ, **env}, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0 and r.stdout.strip().endswith("OK"), (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
