@@ -36,13 +36,17 @@ CSRC = os.path.join(ROOT, "paper_1811_06378_amd", "csrc")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fht_pass_kernel_last_dense4096_traffic.txt")
 
 
+# the sources the forward pass kernels and their launches are built from
+PASS_SOURCES = ("fht_api.hip", "fht_device.h", "fht_fwd_f32.hip", "fht_internal.h", "fht_launch.h", "fht_misc.hip",
+                "fht_plan.h")
+
+
 def sources_digest() -> str:
-    """sha256 over the kernel sources (name + bytes, sorted)."""
+    """sha256 over the forward pass kernel's sources (name + bytes, in order)."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(CSRC, f), "rb").read())
+    for f in PASS_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
 

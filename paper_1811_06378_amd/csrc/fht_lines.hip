@@ -33,25 +33,31 @@ __global__ __launch_bounds__(256) void fht_peaks_kernel(const T* H, int64_t rows
                                                         unsigned* count)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t r = blockIdx.y;
-    if (c >= cols || r >= rows) return;
-    const T v = H[r * ld + c];
-    if (!((double)v > threshold)) return;
-    const int64_t me = r * cols + c;
-    for (int dr = -radius; dr <= radius; ++dr) {
-        const int64_t rr = r + dr;
-        if (rr < 0 || rr >= rows) continue;
-        for (int dc = -radius; dc <= radius; ++dc) {
-            if (dr == 0 && dc == 0) continue;
-            int64_t cc = c + dc;
-            if (cc < 0) cc += cols;
-            if (cc >= cols) cc -= cols;
-            const T u = H[rr * ld + cc];
-            if (u > v || (u == v && rr * cols + cc < me)) return;
+    if (c >= cols) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {  // grid y capped at 65535
+        const T v = H[r * ld + c];
+        if (!((double)v > threshold)) continue;
+        const int64_t me = r * cols + c;
+        bool peak = true;
+        for (int dr = -radius; dr <= radius && peak; ++dr) {
+            const int64_t rr = r + dr;
+            if (rr < 0 || rr >= rows) continue;
+            for (int dc = -radius; dc <= radius; ++dc) {
+                if (dr == 0 && dc == 0) continue;
+                int64_t cc = c + dc;
+                if (cc < 0) cc += cols;
+                if (cc >= cols) cc -= cols;
+                const T u = H[rr * ld + cc];
+                if (u > v || (u == v && rr * cols + cc < me)) {
+                    peak = false;
+                    break;
+                }
+            }
         }
+        if (!peak) continue;
+        const unsigned slot = atomicAdd(count, 1u);
+        if ((int)slot < max_out) out[slot] = me;
     }
-    const unsigned slot = atomicAdd(count, 1u);
-    if ((int)slot < max_out) out[slot] = me;
 }
 
 __global__ void fht_zero_u32_kernel(unsigned* p) { *p = 0u; }
@@ -122,12 +128,12 @@ int fht_peaks(const void* hough, int t, int64_t rows, int64_t cols, int64_t ld, 
 {
     if (!hough || !out || !count) return fail(FHT_ERR_INVALID, "null pointer");
     if (t != FHT_I32 && t != FHT_F32) return fail(FHT_ERR_INVALID, "Hough type must be I32 or F32");
-    if (rows < 1 || cols < 1 || ld < cols || rows > 65535) return fail(FHT_ERR_INVALID, "bad Hough shape");
+    if (rows < 1 || cols < 1 || ld < cols) return fail(FHT_ERR_INVALID, "bad Hough shape");
     if (radius < 1 || radius > 64 || 2 * radius + 1 > cols) return fail(FHT_ERR_INVALID, "radius %d", radius);
     if (max_out < 1) return fail(FHT_ERR_INVALID, "max_out %d", max_out);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(fht_zero_u32_kernel, dim3(1), dim3(1), 0, s, count);
-    const dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows);
+    const dim3 grid((unsigned)((cols + 255) / 256), (unsigned)(rows < 65535 ? rows : 65535));
     if (t == FHT_I32)
         hipLaunchKernelGGL(fht_peaks_kernel<int>, grid, dim3(256), 0, s, (const int*)hough, rows, cols, ld, radius,
                            threshold, out, max_out, count);

@@ -92,3 +92,14 @@ def test_detect_rasterized_lines():
         ok = [s for s in segs if s and abs(s[0][0] - x0) <= 2 and s[0][1] == 0
               and abs(s[1][0] - (x0 + t * (h - 1))) <= 2 and s[1][1] == h - 1]
         assert ok, (x0, t, segs)
+
+
+def test_peaks_on_a_tall_image():
+    """More rows than one grid dimension holds: the kernel strides over rows."""
+    H = np.zeros((70001, 16), dtype=np.int32)
+    H[5, 3] = 7
+    H[69999, 12] = 9
+    H[40000, 0] = 4
+    found, total = fht.peaks(dev(H), radius=2, threshold=0)
+    assert total == 3
+    assert [(r, c) for _, r, c in found] == [(69999, 12), (5, 3), (40000, 0)]
