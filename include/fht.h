@@ -60,7 +60,9 @@ enum fht_status {
     FHT_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
     FHT_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required */
     FHT_ERR_HIP = -4,         /* a HIP runtime call or launch failed */
-    FHT_ERR_TIMEOUT = -5      /* a dependency wait in the batch kernel expired */
+    FHT_ERR_TIMEOUT = -5      /* reserved; the opt-in persistent engine (FHT_ENGINE=1)
+                                 records an expired dependency wait as a nonzero
+                                 word 1 of the workspace instead */
 };
 
 enum fht_dtype { FHT_U8 = 0, FHT_I32 = 1, FHT_F32 = 2 };

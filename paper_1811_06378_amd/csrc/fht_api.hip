@@ -271,7 +271,8 @@ int append_engine_groups(const QuadGeom* gs, const PassDesc (*descs)[4], int nq,
 
 // Iterations of the bounded dependency wait (each sleeps ~256 cycles plus
 // the atomic's round trip): far beyond any legitimate wait, short enough that
-// a planner error surfaces as FHT_ERR_TIMEOUT within seconds.
+// a planner error ends the launch within seconds, with word 1 of the
+// workspace set to nonzero (the engine's error flag) instead of a hang.
 int engine_spin_limit()
 {
     static int lim = -1;
