@@ -369,8 +369,15 @@ def shift(hough: torch.Tensor, w: int, h: int, inverse: bool = False, out: torch
     return out
 
 
+def adjoint_workspace_size(w: int, h: int, quads="full", dtype=torch.float32) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().fht_adjoint_workspace_size(w, h, _quads(quads), _acc_code(dtype), ctypes.byref(b)),
+           "fht_adjoint_workspace_size")
+    return b.value
+
+
 def adjoint(grad: torch.Tensor, w: int, h: int, quads="full", shifted: bool = False,
-            out: torch.Tensor | None = None) -> torch.Tensor:
+            out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Transpose of forward: Hough-shaped gradient -> h x w image gradient."""
     _check_2d(grad, "grad")
     t = _acc_code(grad.dtype)
@@ -378,11 +385,11 @@ def adjoint(grad: torch.Tensor, w: int, h: int, quads="full", shifted: bool = Fa
     if out is None:
         out = torch.empty((h, w), dtype=grad.dtype, device=grad.device)
     _check_2d(out, "out")
-    b = ctypes.c_size_t()
-    _check(lib().fht_adjoint_workspace_size(w, h, q, t, ctypes.byref(b)), "fht_adjoint_workspace_size")
-    ws = _workspace(b.value, grad.device)
+    if workspace is None:
+        workspace = _workspace(adjoint_workspace_size(w, h, q, grad.dtype), grad.device)
     rc = lib().fht_adjoint(grad.data_ptr(), t, grad.stride(0), out.data_ptr(), out.stride(0), w, h, q,
-                           FHT_FLAG_SHIFTED if shifted else 0, ws.data_ptr(), ws.numel(), _stream())
+                           FHT_FLAG_SHIFTED if shifted else 0, workspace.data_ptr(),
+                           workspace.numel() * workspace.element_size(), _stream())
     _check(rc, "fht_adjoint")
     return out
 
