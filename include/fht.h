@@ -280,6 +280,24 @@ int fht_peaks(const void* hough, int t, int64_t rows, int64_t cols, int64_t ld, 
 int fht_timing_enable(int on);
 int fht_timing_report(int index, char* name, int name_cap, int64_t* launches, double* total_ms);
 
+/*
+ * Stage-fusion depth.  A quadrant of n = 2^k rows runs its k stages in the
+ * fewest passes of at most 6 stages; how the stages are split among the
+ * passes is a free choice (each pass 3..6 stages).  By default the larger
+ * passes come first.  fht_set_pass_split sets the split used for k from now
+ * on by every call in the process (npass = 0 restores the default; npass must
+ * be the fewest passes, each entry 3..6, summing to k; k in 3..16).
+ * fht_autotune times every candidate split for the stage counts of an h x w
+ * full transform (dtype pair in_t/acc_t) with HIP events on `stream`, `reps`
+ * calls each, on buffers it allocates and frees itself (it synchronises; not
+ * for the hot path), and keeps the fastest with fht_set_pass_split.  Splits
+ * change band widths: query workspace sizes after tuning (a call with a
+ * short workspace returns FHT_ERR_WORKSPACE).  Results are bit-identical for
+ * every split: the additions of each stage do not depend on the grouping.
+ */
+int fht_set_pass_split(int k, int npass, const int* passes);
+int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream);
+
 /* Stage-fusion split chosen for a side (number of passes and stages per pass),
  * for inspection and tests.  passes[] receives up to 4 entries. */
 int fht_pass_split(int side, int* npass, int* passes);

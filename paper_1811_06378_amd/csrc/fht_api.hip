@@ -6,6 +6,9 @@
 #include "fht_internal.h"
 #include "fht_plan.h"
 
+#include <mutex>
+#include <vector>
+
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -46,6 +49,13 @@ int ilog2(int64_t p)
 
 // Stage-fusion split: k stages in ceil(k/6) passes of 3..6 stages, larger
 // passes first (k <= 2 runs as one direct pass).
+// Stage split per k, set by fht_set_pass_split / fht_autotune (npass 0:
+// the default rule).  Read at planning time only.
+static std::mutex g_split_mu;
+static int g_split[32][5];
+
+static int default_passes(int k) { return (k + kMaxG - 1) / kMaxG; }
+
 void pass_split(int k, int* npass, int* G)
 {
     if (k <= 2) {
@@ -53,10 +63,37 @@ void pass_split(int k, int* npass, int* G)
         G[0] = k;
         return;
     }
-    const int np = (k + kMaxG - 1) / kMaxG;
+    {
+        std::lock_guard<std::mutex> lock(g_split_mu);
+        if (k < 32 && g_split[k][0] > 0) {
+            *npass = g_split[k][0];
+            for (int i = 0; i < *npass; ++i) G[i] = g_split[k][1 + i];
+            return;
+        }
+    }
+    // fewest passes of at most kMaxG stages, larger first
+    const int np = default_passes(k);
     const int base = k / np, rem = k % np;
     for (int i = 0; i < np; ++i) G[i] = base + (i < rem ? 1 : 0);
     *npass = np;
+}
+
+// Every split of k into the fewest passes of 3..kMaxG stages.
+static std::vector<std::vector<int>> split_candidates(int k)
+{
+    std::vector<std::vector<int>> out;
+    const int np = default_passes(k);
+    std::vector<int> cur(np, 3);
+    for (;;) {
+        int sum = 0;
+        for (int g : cur) sum += g;
+        if (sum == k) out.push_back(cur);
+        int i = np - 1;
+        while (i >= 0 && cur[i] == kMaxG) cur[i--] = 3;
+        if (i < 0) break;
+        ++cur[i];
+    }
+    return out;
 }
 
 // Geometry of quadrant q (1..4) of an h x w image; S1 != 0 adds the range shear
@@ -425,6 +462,107 @@ int fht_pass_split(int side, int* npass, int* passes)
     int G[4];
     pass_split(ilog2(pow2_ceil(side)), npass, G);
     for (int i = 0; i < *npass; ++i) passes[i] = G[i];
+    return FHT_OK;
+}
+
+int fht_set_pass_split(int k, int npass, const int* passes)
+{
+    if (k < 3 || k > 16) return fail(FHT_ERR_INVALID, "k %d outside 3..16", k);
+    if (npass == 0) {
+        std::lock_guard<std::mutex> lock(g_split_mu);
+        g_split[k][0] = 0;
+        return FHT_OK;
+    }
+    if (!passes) return fail(FHT_ERR_INVALID, "null passes");
+    if (npass != default_passes(k))
+        return fail(FHT_ERR_INVALID, "k = %d takes %d passes, not %d", k, default_passes(k), npass);
+    int sum = 0;
+    for (int i = 0; i < npass; ++i) {
+        if (passes[i] < 3 || passes[i] > kMaxG) return fail(FHT_ERR_INVALID, "pass of %d stages", passes[i]);
+        sum += passes[i];
+    }
+    if (sum != k) return fail(FHT_ERR_INVALID, "stages sum to %d, not %d", sum, k);
+    std::lock_guard<std::mutex> lock(g_split_mu);
+    g_split[k][0] = npass;
+    for (int i = 0; i < npass; ++i) g_split[k][1 + i] = passes[i];
+    return FHT_OK;
+}
+
+int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream)
+{
+    int rc = check_sides(w, h);
+    if (rc) return rc;
+    if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
+    if (reps < 1 || reps > 1000) return fail(FHT_ERR_INVALID, "reps %d outside 1..1000", reps);
+    const int kh = ilog2(pow2_ceil(h)), kw = ilog2(pow2_ceil(w));
+    // the stage counts with more than one candidate split
+    std::vector<int> ks;
+    for (int k : {kh, kw})
+        if (k >= 7 && split_candidates(k).size() > 1 && (ks.empty() || ks[0] != k)) ks.push_back(k);
+    if (ks.empty()) return FHT_OK;
+    std::vector<std::vector<int>> ca = split_candidates(ks[0]);
+    std::vector<std::vector<int>> cb = ks.size() > 1 ? split_candidates(ks[1]) : std::vector<std::vector<int>>{{}};
+    // buffers for the largest workspace over every combination
+    size_t ws_max = 0;
+    for (auto& a : ca)
+        for (auto& b : cb) {
+            fht_set_pass_split(ks[0], (int)a.size(), a.data());
+            if (ks.size() > 1) fht_set_pass_split(ks[1], (int)b.size(), b.data());
+            size_t need = 0;
+            fht_workspace_size(w, h, FHT_FULL, in_t, acc_t, &need);
+            ws_max = need > ws_max ? need : ws_max;
+        }
+    int64_t rows, cols;
+    fht_hough_shape(w, h, FHT_FULL, &rows, &cols);
+    const size_t in_bytes = (size_t)w * h * (in_t == FHT_U8 ? 1 : 4);
+    void *img = nullptr, *hough = nullptr, *ws = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&img, in_bytes);
+    if (e == hipSuccess) e = hipMalloc(&hough, (size_t)rows * cols * 4);
+    if (e == hipSuccess) e = hipMalloc(&ws, ws_max > 256 ? ws_max : 256);
+    if (e == hipSuccess) e = hipMemsetAsync(img, 0, in_bytes, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = -1.f;
+    std::vector<int> best_a, best_b;
+    for (auto& a : ca) {
+        for (auto& b : cb) {
+            if (e != hipSuccess) break;
+            fht_set_pass_split(ks[0], (int)a.size(), a.data());
+            if (ks.size() > 1) fht_set_pass_split(ks[1], (int)b.size(), b.data());
+            rc = fht_forward(img, in_t, w, h, w, hough, acc_t, cols, FHT_FULL, 0, ws, ws_max > 256 ? ws_max : 256,
+                             stream);  // warm-up
+            if (rc) break;
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+            for (int r = 0; r < reps && rc == FHT_OK; ++r)
+                rc = fht_forward(img, in_t, w, h, w, hough, acc_t, cols, FHT_FULL, 0, ws,
+                                 ws_max > 256 ? ws_max : 256, stream);
+            if (rc) break;
+            if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (best < 0.f || ms < best) {
+                best = ms;
+                best_a = a;
+                best_b = b;
+            }
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipStreamSynchronize(s);
+    hipFree(img);
+    hipFree(hough);
+    hipFree(ws);
+    // keep the fastest (or the default rule if timing failed)
+    fht_set_pass_split(ks[0], 0, nullptr);
+    if (ks.size() > 1) fht_set_pass_split(ks[1], 0, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (rc) return rc;
+    fht_set_pass_split(ks[0], (int)best_a.size(), best_a.data());
+    if (ks.size() > 1) fht_set_pass_split(ks[1], (int)best_b.size(), best_b.data());
     return FHT_OK;
 }
 

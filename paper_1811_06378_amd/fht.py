@@ -16,6 +16,7 @@ Names follow the C ABI in include/fht.h:
   FHTFunction                                 autograd wrapper
   BatchPlan                                   batched forward (graph-capturable)
   cell_segment / peaks / detect_lines          Hough cell -> image segment (sections 3.2, 3.3)
+  set_pass_split / autotune                   stage-fusion depth per pass (tuned on the device)
   timing_enable / timing_report               per-kernel launch times (HIP events)
 """
 from __future__ import annotations
@@ -72,6 +73,8 @@ SIGNATURES = {
     "fht_range_adjoint": (_I, [_P, _I, _I64, _I, _I, _I, _P, _I64, _I, _I, _P, _SZ, _P]),
     "fht_cell_segment": (_I, [_I, _I, _U, _I64, _I64, _I, _PI32]),
     "fht_peaks": (_I, [_P, _I, _I64, _I64, _I64, _I, ctypes.c_double, _P, _I, _P, _P]),
+    "fht_set_pass_split": (_I, [_I, _I, ctypes.POINTER(_I)]),
+    "fht_autotune": (_I, [_I, _I, _I, _I, _I, _P]),
     "fht_timing_enable": (_I, [_I]),
     "fht_timing_report": (_I, [_I, ctypes.c_char_p, _I, _PI64, ctypes.POINTER(ctypes.c_double)]),
 }
@@ -174,6 +177,24 @@ def pass_split(side: int):
     arr = (ctypes.c_int * 4)()
     _check(lib().fht_pass_split(side, ctypes.byref(n), arr), "fht_pass_split")
     return [arr[i] for i in range(n.value)]
+
+
+def set_pass_split(k: int, passes=None):
+    """Stage split for quadrants of 2^k rows (None restores the default)."""
+    if passes is None:
+        _check(lib().fht_set_pass_split(k, 0, None), "fht_set_pass_split")
+        return
+    arr = (ctypes.c_int * len(passes))(*passes)
+    _check(lib().fht_set_pass_split(k, len(passes), arr), "fht_set_pass_split")
+
+
+def autotune(w: int, h: int, in_dtype=torch.float32, reps: int = 20):
+    """Time every candidate stage split for an h x w full transform on the
+    current device and keep the fastest (fht_autotune); returns the splits
+    now used for both sides."""
+    it, at, _ = _dtypes(in_dtype)
+    _check(lib().fht_autotune(w, h, it, at, reps, _stream()), "fht_autotune")
+    return pass_split(h), pass_split(w)
 
 
 def workspace_size(w: int, h: int, quads="full", in_dtype=torch.float32) -> int:

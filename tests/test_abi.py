@@ -156,3 +156,25 @@ def test_range_scaled_shape_and_validation():
     assert (r.value, c.value) == (41, 128 + 32)
     assert L.fht_range_scaled_shape(100, 64, 0, 2, 5, 40, 0, ctypes.byref(r), ctypes.byref(c)) == fht.FHT_ERR_INVALID
     assert L.fht_range_scaled_shape(100, 64, 65, 1, 5, 40, 0, ctypes.byref(r), ctypes.byref(c)) == fht.FHT_ERR_INVALID
+
+
+def test_set_pass_split_validation_and_roundtrip():
+    try:
+        assert fht.pass_split(1024) == [5, 5]
+        fht.set_pass_split(10, [4, 6])
+        assert fht.pass_split(1024) == [4, 6]
+        assert fht.pass_split(2048) == [6, 5]          # other k untouched
+        for bad in ([5, 6], [2, 8], [10], [3, 3, 4]):
+            with pytest.raises(ValueError):
+                fht.set_pass_split(10, bad)
+        with pytest.raises(ValueError):
+            fht.set_pass_split(2, [2])
+        # the first band is other + 2^G1 - 1 columns (origin rounded to 64):
+        # a deeper first pass never needs less workspace
+        fht.set_pass_split(10, [6, 4])
+        wide = fht.workspace_size(1024, 1024)
+        fht.set_pass_split(10, [4, 6])
+        assert fht.workspace_size(1024, 1024) <= wide
+    finally:
+        fht.set_pass_split(10, None)
+    assert fht.pass_split(1024) == [5, 5]
