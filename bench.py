@@ -109,8 +109,16 @@ def cpu_baseline(img, target_s: float = 10.0):
         total += time.perf_counter() - t
         reps += 1
     px = x.shape[0] * x.shape[1] * reps
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(px / total / 1e9, 6), "unit": "Gpixels/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": "%d full float64 transform(s) of the same 4096x4096 image, %.1f s" % (reps, total)}
 
 
