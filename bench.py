@@ -243,6 +243,8 @@ def main():
     fht.timing_enable(False)
     ms_fwd = e0.elapsed_time(e1) / args.steps
     kernels = fht.timing_report()
+    # the same steps without the per-launch events, to show what they cost
+    ms_plain = _timed(step, args.steps, 1, torch)
     px = side * side
     value = px / (ms_fwd * 1e-3) / 1e9
 
@@ -254,6 +256,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_fwd, 4),
+        "ms_per_step_without_launch_events": round(ms_plain, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -204,18 +204,6 @@ void placement(int w, int h, unsigned quads, int q, int* base, int* sign, int* s
     *skip = -1;
 }
 
-// FHT_NT=0 writes the Hough image with ordinary stores instead of streaming
-// (non-temporal) ones.
-static int stream_stores()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("FHT_NT");
-        v = (e && e[0] == '0') ? 0 : 1;
-    }
-    return v;
-}
-
 // Descriptor of forward pass p of quadrant geometry g.
 PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int w, int h, int64_t ld_img, void* hough,
                         int64_t ld_hough, unsigned char* ws, int S1, int row_limit_final, int base, int sign,
@@ -264,7 +252,6 @@ PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int w, int h,
         // unmirrored, [1, 1 + n - s) mirrored; not with a shear
         d.black_lo = g.mirror ? 1 : g.other;
         d.black_ok = (S1 == 0) ? 1 : 0;
-        d.stream_store = stream_stores();
     } else {
         d.dst = ws + g.band_byte_off[p];
         d.dst_ld = g.band_ld[p];

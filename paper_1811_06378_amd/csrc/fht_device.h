@@ -157,18 +157,6 @@ __device__ __forceinline__ void store8(T* p, const T (&v)[8])
     *reinterpret_cast<V*>(p + 4) = b;
 }
 
-// Streaming store for the final Hough image (written once, never re-read here).
-template <typename T>
-__device__ __forceinline__ void store8_stream(T* p, const T (&v)[8])
-{
-    typedef typename vec4u<T>::type V;
-    V a, b;
-    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
-    b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
-    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
-    __builtin_nontemporal_store(b, reinterpret_cast<V*>(p + 4));
-}
-
 template <typename T>
 __device__ __forceinline__ void reverse8(T (&v)[8])
 {
@@ -564,8 +552,7 @@ __device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, in
                 T v[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) v[c] = d.mirror ? b[rho][7 - c] : b[rho][c];
-                if (d.stream_store) store8_stream<T>(dst + e0, v);
-                else store8<T>(dst + e0, v);
+                store8<T>(dst + e0, v);
             } else {
 #pragma unroll
                 for (int c = 0; c < 8; ++c)

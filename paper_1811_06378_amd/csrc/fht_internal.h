@@ -56,7 +56,6 @@ struct PassDesc {
     int roll_a, roll_b;
     int black_lo;         // last pass: xi in [black_lo, black_lo + n - s) is structurally zero in row s
     int black_ok;         // 1: tiles wholly inside that zone are written as zeros without loads
-    int stream_store;     // 1: non-temporal stores for the Hough image
     int scale_num, scale_den;  // first pass: source sample floor(x * den / num) along the
                                // sheared axis (section 4 scale); 0 = no scaling
 };

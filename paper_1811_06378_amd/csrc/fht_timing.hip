@@ -2,6 +2,9 @@
 // pass kernel the library enqueues is bracketed by two HIP events recorded
 // on the launch stream; fht_timing_report sums the elapsed times per kernel
 // instantiation.  Nothing is recorded while the stream is being captured.
+// The events are created without the system-scope fence: with it, each
+// record wrote back the caches and the forward step of a 4096^2 image took
+// about 27 us longer.
 #include "fht.h"
 #include "fht_internal.h"
 #include "fht_plan.h"
@@ -82,8 +85,10 @@ int timing_begin(const std::string& name, hipStream_t s)
     if (dev != g_device) return -1;
     const size_t slot = g_recs.size();
     while (g_events.size() < 2 * (slot + 1)) {
+        // timing-only events: no system-scope fence, which would write back
+        // and invalidate the caches at every record and slow the next launch
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
         g_events.push_back(e);
     }
     if (hipEventRecord(g_events[2 * slot], s) != hipSuccess) return -1;

@@ -1,0 +1,87 @@
+"""Launch timing (fht_timing_enable / fht_timing_report): the per-kernel HIP
+events that the benchmark's roofline figure is computed from."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1811_06378_amd import fht, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _forward(img, reps):
+    out = None
+    for _ in range(reps):
+        out = fht.forward(img)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_forward_launches_are_counted_per_kernel():
+    img = torch.from_numpy(synth.random_image(1024, 1024, "f32", seed=1)).cuda()
+    _forward(img, 1)
+    fht.timing_enable(True)
+    try:
+        _forward(img, 3)
+    finally:
+        fht.timing_enable(False)
+    rep = fht.timing_report()
+    # 1024: two passes of 5 stages (GB = 2), first pass from the image, last to the Hough image
+    first = "fht::fht_pass_kernel<float, float, 2, true, false, 0>"
+    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0>"
+    assert set(rep) == {first, last}, rep
+    for name in (first, last):
+        launches, total_ms = rep[name]
+        assert launches == 3
+        assert 0.0 < total_ms / launches < 50.0
+
+
+def test_enable_clears_and_disable_stops_recording():
+    img = torch.from_numpy(synth.random_image(300, 200, "u8", seed=2)).cuda()
+    fht.timing_enable(True)
+    _forward(img, 2)
+    fht.timing_enable(True)  # starts over
+    _forward(img, 1)
+    fht.timing_enable(False)
+    _forward(img, 4)  # not recorded
+    rep = fht.timing_report()
+    assert rep and all(n == 1 for n, _ in rep.values()), rep
+
+
+def test_timing_does_not_change_results():
+    img = torch.from_numpy(synth.random_image(517, 389, "f32", seed=3)).cuda()
+    ref = _forward(img, 1).cpu()
+    fht.timing_enable(True)
+    try:
+        got = _forward(img, 1).cpu()
+    finally:
+        fht.timing_enable(False)
+    assert torch.equal(ref, got)
+
+
+def test_nothing_recorded_under_graph_capture():
+    sizes = [(100, 90), (64, 200)]
+    imgs = [torch.from_numpy(synth.random_image(h, w, "u8", seed=i)).cuda() for i, (h, w) in enumerate(sizes)]
+    plan = fht.BatchPlan(sizes, in_dtype=torch.uint8)
+    table = plan.pointer_table(imgs)
+    packed = plan.output()
+    plan.run(table, packed)
+    torch.cuda.synchronize()
+    want = packed.clone()
+    fht.timing_enable(True)
+    try:
+        g = plan.capture(table, packed)  # one eager warm-up run, then the capture
+        torch.cuda.synchronize()
+        eager = sum(n for n, _ in fht.timing_report().values())
+        packed.zero_()
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(packed, want)
+    finally:
+        fht.timing_enable(False)
+    rep = fht.timing_report()
+    # only the eager warm-up launches were recorded; replays add none
+    assert sum(n for n, _ in rep.values()) == eager > 0
+    del g
+    np.testing.assert_array_equal(packed.cpu().numpy(), want.cpu().numpy())

@@ -1,7 +1,6 @@
-"""The opt-in launch variants (read once per process from the environment):
-FHT_ENGINE=1, the persistent queue engine, and FHT_NT=1, streaming stores
-of the Hough image.  Each runs in one child process that checks a few
-forward transforms against the oracle and prints OK."""
+"""The opt-in launch variant (read once per process from the environment):
+FHT_ENGINE=1, the persistent queue engine.  It runs in a child process that
+checks a few forward transforms against the oracle and prints OK."""
 import os
 import subprocess
 import sys
@@ -30,7 +29,7 @@ print("OK")
 """
 
 
-@pytest.mark.parametrize("env", [{"FHT_ENGINE": "1"}, {"FHT_NT": "1"}])
+@pytest.mark.parametrize("env", [{"FHT_ENGINE": "1"}])
 def test_variant_matches_oracle(env):
     code = CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"))
     r = subprocess.run([sys.executable, "-c", code], env={**os.environ, **env}, capture_output=True, text=True,
