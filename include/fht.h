@@ -276,8 +276,14 @@ int fht_peaks(const void* hough, int t, int64_t rows, int64_t cols, int64_t ld, 
  * name_cap bytes with the terminator), the number of launches and their
  * summed elapsed time in milliseconds; FHT_ERR_INVALID past the last one.
  * The device is the one current at fht_timing_enable(1).
+ * fht_timing_filter(substr) restricts recording to the kernels whose name
+ * contains substr (NULL or "" records every kernel again); the string is
+ * copied, at most 255 bytes.  Each pair of events delays the next launch by
+ * a few microseconds, so timing only the kernel of interest disturbs the
+ * rest of the stream less.
  */
 int fht_timing_enable(int on);
+int fht_timing_filter(const char* substr);
 int fht_timing_report(int index, char* name, int name_cap, int64_t* launches, double* total_ms);
 
 /*

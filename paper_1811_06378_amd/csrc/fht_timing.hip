@@ -28,6 +28,7 @@ struct Record {
 
 std::atomic<bool> g_on{false};
 std::mutex g_mu;
+std::string g_filter;  // record only kernels whose name contains it
 int g_device = -1;
 std::vector<hipEvent_t> g_events;  // 2 per record: begin, end
 std::vector<Record> g_recs;
@@ -81,6 +82,7 @@ int timing_begin(const std::string& name, hipStream_t s)
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     std::lock_guard<std::mutex> lock(g_mu);
     if (!g_on.load() || g_recs.size() >= kMaxRecords) return -1;
+    if (!g_filter.empty() && name.find(g_filter) == std::string::npos) return -1;
     if (g_device < 0) g_device = dev;
     if (dev != g_device) return -1;
     const size_t slot = g_recs.size();
@@ -128,6 +130,13 @@ int fht_timing_enable(int on)
         }
     }
     g_on.store(on != 0);
+    return FHT_OK;
+}
+
+int fht_timing_filter(const char* substr)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_filter.assign(substr ? substr : "", substr ? strnlen(substr, 255) : 0);
     return FHT_OK;
 }
 

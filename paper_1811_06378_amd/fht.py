@@ -76,6 +76,7 @@ SIGNATURES = {
     "fht_set_pass_split": (_I, [_I, _I, ctypes.POINTER(_I)]),
     "fht_autotune": (_I, [_I, _I, _I, _I, _I, _P]),
     "fht_timing_enable": (_I, [_I]),
+    "fht_timing_filter": (_I, [ctypes.c_char_p]),
     "fht_timing_report": (_I, [_I, ctypes.c_char_p, _I, _PI64, ctypes.POINTER(ctypes.c_double)]),
 }
 
@@ -493,6 +494,11 @@ def timing_enable(on: bool = True):
     """Start (clearing earlier records) or stop recording HIP events around
     every pass kernel launch of the library."""
     _check(lib().fht_timing_enable(int(on)), "fht_timing_enable")
+
+
+def timing_filter(substr=None):
+    """Record only the kernels whose name contains substr (None: all)."""
+    _check(lib().fht_timing_filter(substr.encode() if substr else None), "fht_timing_filter")
 
 
 def timing_report():

@@ -36,6 +36,15 @@ def test_version_and_strings():
         assert L.fht_status_string(rc)
 
 
+def test_timing_filter_and_empty_report_need_no_gpu():
+    # the filter is a host-side string; an empty record set reports nothing
+    fht.timing_filter("fht_pass_kernel<float")
+    fht.timing_filter("x" * 1000)  # truncated, not an error
+    fht.timing_filter(None)
+    fht.timing_enable(False)
+    assert fht.lib().fht_timing_report(10 ** 6, None, 0, None, None) == fht.FHT_ERR_INVALID
+
+
 @pytest.mark.parametrize("w,h,quads,rows,cols", [
     (1, 1, 15, 1, 2), (1024, 1024, 15, 4093, 2048), (4096, 4096, 15, 16381, 8192),
     (100, 37, 15, 2 * (128 + 64) - 3, 192), (100, 37, 1, 64, 192), (100, 37, 4, 128, 192),

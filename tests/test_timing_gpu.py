@@ -85,3 +85,22 @@ def test_nothing_recorded_under_graph_capture():
     assert sum(n for n, _ in rep.values()) == eager > 0
     del g
     np.testing.assert_array_equal(packed.cpu().numpy(), want.cpu().numpy())
+
+
+def test_filter_records_only_matching_kernels():
+    img = torch.from_numpy(synth.random_image(1024, 1024, "f32", seed=4)).cuda()
+    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0>"
+    fht.timing_filter("2, false, true, 0>")
+    fht.timing_enable(True)
+    try:
+        _forward(img, 2)
+    finally:
+        fht.timing_enable(False)
+        fht.timing_filter(None)
+    rep = fht.timing_report()
+    assert list(rep) == [last] and rep[last][0] == 2, rep
+    # the filter is cleared: both passes again
+    fht.timing_enable(True)
+    _forward(img, 1)
+    fht.timing_enable(False)
+    assert len(fht.timing_report()) == 2
