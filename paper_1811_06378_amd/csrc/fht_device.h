@@ -168,22 +168,26 @@ __device__ __forceinline__ void reverse8(T (&v)[8])
     }
 }
 
-template <typename TIn>
-__device__ __forceinline__ bool vec_ok(const TIn* p)
-{
-    if constexpr (sizeof(TIn) == 1) return (reinterpret_cast<uintptr_t>(p) & 3) == 0;
-    else return true;
-}
-
+// 8 consecutive source elements.  For bytes at any address: the two aligned
+// dwords from the dword holding p[0], plus the dword holding p[7] when p is
+// not dword-aligned (else that dword again), funnel-shifted by the byte
+// offset.  Every dword read holds at least one of the 8 wanted bytes, so no
+// read reaches a page the wanted bytes do not touch.
 template <typename TIn, typename T>
 __device__ __forceinline__ void load8_src(const TIn* p, T (&v)[8])
 {
     if constexpr (sizeof(TIn) == 1) {
-        const u32x2u w = *reinterpret_cast<const u32x2u*>(p);
+        const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+        const uint32_t* base = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3) * 8u;
+        const u32x2u w = *reinterpret_cast<const u32x2u*>(base);
+        const uint32_t w2 = base[sh ? 2 : 1];
+        const uint32_t lo = __builtin_amdgcn_alignbit(w.y, w.x, sh);
+        const uint32_t hi = __builtin_amdgcn_alignbit(w2, w.y, sh);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            v[c] = (T)((w.x >> (8 * c)) & 0xFFu);
-            v[4 + c] = (T)((w.y >> (8 * c)) & 0xFFu);
+            v[c] = (T)((lo >> (8 * c)) & 0xFFu);
+            v[4 + c] = (T)((hi >> (8 * c)) & 0xFFu);
         }
     } else {
         load8<T>(reinterpret_cast<const T*>(p), v);
@@ -387,7 +391,7 @@ __device__ __forceinline__ bool issue_image_row(const PassDesc& d, int R, int xr
     const TIn* p = reinterpret_cast<const TIn*>(d.src) + (long long)R * d.src_ld;
     e0 = lane_run_start(xrow, -shear_of_row(R, d.S1, d.n), lane, W, d.mirror);
     const bool row_ok = R < d.img_h;
-    const bool fast = row_ok && e0 + 8 <= d.img_w && vec_ok<TIn>(p + e0);
+    const bool fast = row_ok && e0 + 8 <= d.img_w;
     const bool zero = !row_ok || (e0 >= d.img_w && e0 + 8 <= W);
     load8_src<TIn, T>(fast ? p + e0 : zero_page<TIn>(), v);
     if (d.mirror) reverse8(v);
@@ -437,7 +441,7 @@ __device__ __forceinline__ void load_rows_transposed(const PassDesc& d, int R0, 
         const int e = run_col(e0, c, W, d.mirror);
         const TIn* p = img + (long long)e * d.src_ld + R0;
         const bool inside = e < d.img_h;
-        const bool fast = inside && all_cols && vec_ok<TIn>(p);
+        const bool fast = inside && all_cols;
         T t[8];
         load8_src<TIn, T>(fast ? p : zero_page<TIn>(), t);
 #pragma unroll
