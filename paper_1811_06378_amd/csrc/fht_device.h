@@ -602,6 +602,11 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         const int B = mu >> j0;
         const int u = mu & ((1 << j0) - 1);
         const bool active = (mu < n_mini) && ((u << G) <= d.row_limit);
+        // Raised issue priority while this wave issues its loads, so that
+        // they go out ahead of the other resident workgroup's arithmetic
+        // (measured: last pass of 4096^2 f32 about 2% faster; raising it
+        // for the stores as well gained nothing).
+        __builtin_amdgcn_s_setprio(2);
         if (!active) {
 #pragma unroll
             for (int r = 0; r < 8; ++r) zero8(a[r]);
@@ -640,6 +645,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         fwd_stage<T, 0, OP>(a);
         fwd_stage<T, 1, OP>(a);
         fwd_stage<T, 2, OP>(a);
