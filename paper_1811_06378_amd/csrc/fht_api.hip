@@ -816,6 +816,12 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
         d.shifted = shifted;
         d.roll_a = roll_a;
         d.roll_b = roll_b;
+        // the gradient on the zone of section 3.2 (case c) reaches only the
+        // zero padding, never an image pixel, so it is read as zero: the
+        // image gradient does not change, not even in rounding (every sum
+        // that reaches an image pixel has the same terms)
+        d.black_lo = g.mirror ? 1 : g.other;
+        d.black_ok = 1;
     } else {
         d.src = ws + g.band_byte_off[p];
         d.src_ld = g.band_ld[p];
@@ -990,7 +996,10 @@ int fht_range_adjoint(const void* grad, int t, int64_t ld_grad, int S1, int S, i
     // the last one writes the full-width source gradient a0 (n x W)
     for (int p = g.npass - 1; p >= 0; --p) {
         AdjDesc d = make_adj_desc(g, p, grad, ld_grad, nullptr, 0, w, h, ws, 0, 1, -1, 0, 0, 0, 0);
-        if (p == g.npass - 1) d.row_limit = S;
+        if (p == g.npass - 1) {
+            d.row_limit = S;
+            d.black_ok = 0;  // the zone moves with the shear
+        }
         if (p == 0) {
             const int VW = kWinCols - (1 << g.G[0]);
             d.dst = a0;

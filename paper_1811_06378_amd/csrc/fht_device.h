@@ -828,10 +828,17 @@ __device__ __forceinline__ bool adj_issue_hough(const AdjDesc& d, int s_row, int
     const T* src = reinterpret_cast<const T*>(d.src) + (long long)(d.row_base + d.row_sign * s_row) * d.src_ld;
     const int roll = d.shifted ? ((d.roll_a + d.roll_b * s_row) >> 1) : 0;
     e0 = lane_run_start(xrow, roll, lane, W, d.mirror);
-    const bool fast = !skip && e0 + 8 <= W;
+    // the lane's 8 cells xi = xrow + 8*lane .. +7 inside the zero zone of row s
+    bool black = false;
+    if (d.black_ok) {
+        const int x = mod_w(xrow, W) + 8 * lane;  // below W + 512: no second wrap needed
+        const int xm = x >= W ? x - W : x;
+        black = xm >= d.black_lo && xm + 8 <= d.black_lo + d.n - s_row;
+    }
+    const bool fast = !skip && !black && e0 + 8 <= W;
     load8<T>(fast ? src + e0 : zero_page<T>(), v);
     if (d.mirror) reverse8(v);
-    return !skip && !fast;
+    return !skip && !black && !fast;
 }
 
 template <typename T>

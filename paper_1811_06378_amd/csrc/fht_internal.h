@@ -83,6 +83,8 @@ struct AdjDesc {
     int row_base, row_sign, skip_row;  // Hough source row mapping
     int row_limit;        // Hough rows (shifts) above it read as zero (angle range: S)
     int shifted, roll_a, roll_b;
+    int black_lo;         // Hough source: xi in [black_lo, black_lo + n - s) of row s is
+    int black_ok;         // the structurally zero zone; 1: read it as zero (no shear)
 };
 struct AdjLaunch {
     AdjDesc d[kMaxDescs];

@@ -114,3 +114,24 @@ def test_gradcheck_tiny():
     with torch.no_grad():
         rhs = float((gy.double() * f(v).double()).sum())
     assert abs(lhs - rhs) <= 1e-4 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("h,w,shifted", [(300, 520, False), (1000, 70, False), (129, 257, True)])
+def test_adjoint_ignores_cells_that_reach_no_pixel(h, w, shifted):
+    # Cells whose pattern holds no image pixel (the forward of an all-ones
+    # image is 0 there) cannot reach the image gradient.  The adjoint reads
+    # the structurally zero part of them as zero; huge values there must not
+    # change one bit of the float32 gradient.
+    ones = oracle.full(np.ones((h, w)))
+    if shifted:
+        ones = oracle.fhtshift_full(ones, w, h)
+    mask = ones == 0
+    assert mask.any()
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(ones.shape).astype(np.float32)
+    g2 = g.copy()
+    g2[mask] = 3.0e38
+    a = host(fht.adjoint(dev(g), w, h, shifted=shifted))
+    b = host(fht.adjoint(dev(g2), w, h, shifted=shifted))
+    assert np.array_equal(a, b)
+    assert np.all(np.isfinite(b))
