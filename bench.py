@@ -324,8 +324,20 @@ def main():
         result["sparse1024"] = bench_sparse1024(fht, synth, torch, max(5, args.steps))
 
         imgs512 = [torch.from_numpy(a).cuda() for a in synth.batch512(0)]
+        # stage-fusion depth tuned on this device for every stage count in
+        # the batch (one square image of each padded side), then planned
+        ks = sorted({max(0, (s - 1).bit_length()) for a in imgs512 for s in a.shape})
+        tuned = {}
+        for k in ks:
+            if 7 <= k <= 12:
+                fht.autotune(1 << k, 1 << k, torch.uint8, reps=10)
+                tuned[str(k)] = fht.pass_split(1 << k)
         result["batch512"] = bench_batch(fht, torch, imgs512, 3, 1, "batch512 u8")
         result["batch512"]["workload"] = "512 uint8 images, sides uniform in 64..2048 (seed 0), int32 Hough images"
+        result["batch512"]["tuned_splits"] = tuned
+        for k in ks:
+            if 7 <= k <= 12:
+                fht.set_pass_split(k, None)
         del imgs512
         torch.cuda.empty_cache()
 
