@@ -318,11 +318,19 @@ __device__ __forceinline__ void lds_read8_fixed(const T* p, T (&v)[8])
     for (int c = 0; c < 8; ++c) v[c] = p[((c + O7) & 7) * kPlane + ((c + O7) >> 3)];
 }
 
+// For the writes (the adjoint's exchange), the empty asm statements,
+// distinct per residue, keep the compiler from merging the 8 cases into one
+// with per-element address arithmetic (seven adds and address registers
+// per row); kept apart, the first adjoint pass of 4096^2 f32 is about 4 us
+// faster.  The same for the reads made the forward's first pass 4 us
+// slower, so they are left to the compiler.
 template <int O7, typename T>
 __device__ __forceinline__ void lds_write8_fixed(T* p, const T (&v)[8])
 {
+    asm volatile("; lds row write, residue %0" ::"n"(O7));
 #pragma unroll
     for (int c = 0; c < 8; ++c) p[((c + O7) & 7) * kPlane + ((c + O7) >> 3)] = v[c];
+    asm volatile("; lds row write, residue %0, issued" ::"n"(O7));
 }
 
 // row_lane = row base + lane; off >= 0 (wave-uniform)
