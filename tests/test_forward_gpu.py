@@ -137,3 +137,23 @@ def test_pitched_buffers():
     got = host(out_big)
     assert_equal(got[:, :cols].astype(np.float64), _oracle_full(img), "pitched")
     assert np.all(got[:, cols:] == -7)
+
+
+@pytest.mark.parametrize("col0", [0, 1, 2, 3])
+@pytest.mark.parametrize("pitch", [301, 302, 303, 304])
+def test_byte_image_any_alignment(col0, pitch):
+    """uint8 rows at every start alignment: a view starting col0 bytes into
+    rows of `pitch` bytes (odd pitches misalign every other row).  Runs of 8
+    pixels are read from the aligned dwords that hold them, in all four
+    quadrants (mirrored and transposed), for the full transform and the
+    shifted one."""
+    h, w = 150, 290
+    img = _img(h, w, "u8", seed=11 + col0)
+    big = np.full((h, pitch), 200, dtype=np.uint8)
+    big[:, col0:col0 + w] = img
+    x = dev(big)[:, col0:col0 + w]
+    assert x.stride(0) == pitch
+    want = _oracle_full(img)
+    assert_equal(host(fht.forward(x)).astype(np.float64), want, "u8 col0=%d pitch=%d" % (col0, pitch))
+    got_s = host(fht.forward(x, shifted=True)).astype(np.float64)
+    assert_equal(got_s, oracle.fhtshift_full(want, w, h), "u8 shifted col0=%d pitch=%d" % (col0, pitch))
