@@ -210,7 +210,7 @@ def main():
                     help="instead of the benchmark, run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the transform shards "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the transform shards "
               "by image, quadrant or column band without a collective on the hot path).", file=sys.stderr)
         sys.exit(2)
 

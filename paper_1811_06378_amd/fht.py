@@ -91,8 +91,8 @@ def lib():
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
-                raise FHTError("libfht.so is not built (run __graft_entry__.build() or "
-                               "python paper_1811_06378_amd/build.py); there is no fallback path")
+                raise FHTError("libfht.so is not built (run python paper_1811_06378_amd/build.py); "
+                               "there is no fallback path")
             L = ctypes.CDLL(LIB_PATH)
             for name, (res, args) in SIGNATURES.items():
                 f = getattr(L, name)

@@ -446,7 +446,7 @@ def test_range_adjoint_unsheared_full_range_is_the_quadrant_adjoint(oracle_mod):
 
 
 # ---- scale along the sheared axis in the first iteration (section 4);
-# the nearest-sample resampling is this build's reading (the paper fixes none)
+# the nearest-sample resampling is a reading of that section (the paper fixes none)
 
 @pytest.mark.parametrize("tr", [False, True])
 def test_scale_one_is_the_plain_range(oracle_mod, tr):
