@@ -171,6 +171,41 @@ def batch_graph_ms(fht, torch, imgs, steps):
     return ms
 
 
+def bench_diff16(fht, synth, torch, steps):
+    """The differentiable workload: a 16 x 1024^2 float32 stack through the
+    autograd wrapper, forward plus backward for a fixed upstream gradient
+    (the weighted-square loss's gradient shape), against the same work as a
+    loop of single-image forwards and adjoints."""
+    xs = torch.from_numpy(synth.normal1024(0)).cuda()
+    n, h, w = xs.shape
+    rows, cols = fht.hough_shape(w, h)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    up = torch.rand((n, rows, cols), generator=gen, device="cuda")
+    x = xs.clone().requires_grad_()
+
+    def step():
+        x.grad = None
+        fht.fht(x).backward(up)
+
+    ms = _timed(step, steps, 2, torch)
+    outs = torch.empty((n, rows, cols), device="cuda")
+    grads = torch.empty_like(xs)
+
+    def loop():
+        for i in range(n):
+            fht.forward(xs[i], out=outs[i])
+            fht.adjoint(up[i], w, h, out=grads[i])
+
+    ms_loop = _timed(loop, steps, 2, torch)
+    px = n * h * w
+    log("diff16x1024: autograd fwd+bwd %.3f ms, single-image loop %.3f ms" % (ms, ms_loop))
+    return {"workload": "16 x 1024x1024 float32 (standard normal), forward + backward through the autograd "
+                        "wrapper for a fixed upstream gradient", "unit": "Gpixels/s",
+            "value": round(px / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
+            "single_image_loop": {"value": round(px / (ms_loop * 1e-3) / 1e9, 3), "ms_per_step": round(ms_loop, 4)}}
+
+
 def bench_sparse1024(fht, synth, torch, steps):
     """1024^2 uint8 image: full forward, forward with fhtshift fused into the
     stores, standalone fhtshift of the full image, and the angle range
@@ -335,6 +370,8 @@ def main():
         del imgs8
 
         result["sparse1024"] = bench_sparse1024(fht, synth, torch, max(5, args.steps))
+        result["diff16x1024"] = bench_diff16(fht, synth, torch, max(5, args.steps // 2))
+        torch.cuda.empty_cache()
 
         imgs512 = [torch.from_numpy(a).cuda() for a in synth.batch512(0)]
         # Stage-fusion depth: the default splits against the splits tuned on

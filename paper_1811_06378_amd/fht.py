@@ -433,8 +433,7 @@ class FHTFunction(torch.autograd.Function):
         x = img.contiguous()
         if x.dim() == 2:
             return forward(x, quads, shifted)
-        outs = [forward(x[i], quads, shifted) for i in range(x.shape[0])]
-        return torch.stack(outs)
+        return batch_forward(x, quads, shifted)
 
     @staticmethod
     def backward(ctx, g):
@@ -442,8 +441,81 @@ class FHTFunction(torch.autograd.Function):
         g = g.contiguous()
         if g.dim() == 2:
             return adjoint(g, w, h, ctx.quads, ctx.shifted), None, None
-        outs = [adjoint(g[i], w, h, ctx.quads, ctx.shifted) for i in range(g.shape[0])]
-        return torch.stack(outs), None, None
+        return batch_adjoint(g, w, h, ctx.quads, ctx.shifted), None, None
+
+
+_plan_cache = {}
+_side_streams = {}
+
+
+def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False) -> torch.Tensor:
+    """Hough images of a (batch, h, w) stack of same-size images, into one
+    (batch, rows, cols) tensor.  Without fhtshift and with sides >= 5 this is
+    one batch plan (one launch per pass class for the whole stack, cached per
+    shape); otherwise one forward per image, each written in place."""
+    if x.dim() != 3:
+        raise ValueError("batch_forward takes a (batch, h, w) tensor")
+    x = x.contiguous()
+    n, h, w = x.shape
+    q = _quads(quads)
+    rows, cols = hough_shape(w, h, q)
+    _, _, odt = _dtypes(x.dtype)
+    out = torch.empty((n, rows, cols), dtype=odt, device=x.device)
+    if n == 0:
+        return out
+    if shifted or h < 5 or w < 5 or n == 1:
+        for i in range(n):
+            forward(x[i], q, shifted, out=out[i])
+        return out
+    key = (n, h, w, q, x.dtype, x.device)
+    plan = _plan_cache.get(key)
+    if plan is None:
+        plan = BatchPlan([(h, w)] * n, q, x.dtype, x.device)
+        if plan.offsets != [i * rows * cols for i in range(n)]:
+            raise RuntimeError("batch plan does not lay out equal images back to back")
+        _plan_cache[key] = plan
+    ws = _workspace(plan.workspace_bytes, x.device)
+    plan.run(plan.pointer_table([x[i] for i in range(n)]), out.view(-1), workspace=ws)
+    return out
+
+
+def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool = False,
+                  streams: int = 4) -> torch.Tensor:
+    """Adjoints of a (batch, rows, cols) stack of Hough gradients into one
+    (batch, h, w) tensor.  The images are spread over `streams` side streams
+    (default priority), each with its own workspace, so that the launches of
+    small images overlap; the caller's stream waits for all of them."""
+    if g.dim() != 3:
+        raise ValueError("batch_adjoint takes a (batch, rows, cols) tensor")
+    g = g.contiguous()
+    n = g.shape[0]
+    out = torch.empty((n, h, w), dtype=g.dtype, device=g.device)
+    ns = max(1, min(streams, n))
+    if ns == 1:
+        for i in range(n):
+            adjoint(g[i], w, h, quads, shifted, out=out[i])
+        return out
+    cur = torch.cuda.current_stream(g.device)
+    key = (g.device, ns)
+    if key not in _side_streams:
+        _side_streams[key] = [torch.cuda.Stream(device=g.device) for _ in range(ns)]
+    side = _side_streams[key]
+    wsb = adjoint_workspace_size(w, h, quads, g.dtype)
+    wss = [_workspace(wsb, g.device) for _ in range(ns)]
+    for s in side:
+        s.wait_stream(cur)
+    for i in range(n):
+        s = side[i % ns]
+        with torch.cuda.stream(s):
+            adjoint(g[i], w, h, quads, shifted, out=out[i], workspace=wss[i % ns])
+    for s in side:
+        cur.wait_stream(s)
+        # the buffers were used on s: the allocator must not reuse them before s is done
+        g.record_stream(s)
+        out.record_stream(s)
+        for t in wss:
+            t.record_stream(s)
+    return out
 
 
 def fht(img, quads="full", shifted=False):
@@ -546,7 +618,7 @@ class BatchPlan:
         self.out_elems = tot.value
         self.offsets = [offs[i] for i in range(self.n)]
         self.shapes = [hough_shape(w, h, self.quads) for h, w in self.sizes]
-        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        self._workspace = None
 
     def output(self) -> torch.Tensor:
         return torch.empty(self.out_elems, dtype=self.out_dtype, device=self.device)
@@ -560,9 +632,22 @@ class BatchPlan:
                 raise ValueError("batch image does not match the plan")
         return torch.tensor([x.data_ptr() for x in imgs], dtype=torch.int64, device=self.device)
 
-    def run(self, ptr_table: torch.Tensor, packed: torch.Tensor):
-        rc = lib().fht_batch_forward(self._plan, ptr_table.data_ptr(), packed.data_ptr(), self.workspace.data_ptr(),
-                                     self.workspace.numel(), _stream())
+    @property
+    def workspace(self) -> torch.Tensor:
+        """The plan's own workspace (allocated on first use)."""
+        if self._workspace is None:
+            self._workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        return self._workspace
+
+    def run(self, ptr_table: torch.Tensor, packed: torch.Tensor, workspace: torch.Tensor | None = None):
+        """One batched forward on the current stream.  A workspace passed in
+        (at least workspace_bytes, 256-byte aligned) is used instead of the
+        plan's own, so calls on different streams do not share one."""
+        ws = self.workspace if workspace is None else workspace
+        if ws.numel() < self.workspace_bytes:
+            raise ValueError("batch workspace too small")
+        rc = lib().fht_batch_forward(self._plan, ptr_table.data_ptr(), packed.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     _stream())
         _check(rc, "fht_batch_forward")
         return packed
 
