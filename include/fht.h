@@ -170,6 +170,22 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
                 void* stream);
 
 /*
+ * fht_adjoint of a stack of n same-size gradients (the backward of a stack
+ * of images), with up to 4 images' passes of one kind in each launch: small
+ * images fill the chip together where one alone leaves it mostly idle.
+ * Image i's gradient starts grad_stride elements after image i-1's
+ * (grad_stride >= rows * ld_hough when n > 1), and its output img_stride
+ * elements after (img_stride >= h * ld_img when n > 1).  Every other
+ * argument as fht_adjoint; results equal n calls of fht_adjoint bit for bit.
+ * The workspace (>= fht_adjoint_stack_workspace_size, 256-byte aligned)
+ * holds min(n, 4) single-image workspaces.
+ */
+int fht_adjoint_stack_workspace_size(int w, int h, unsigned quads, int t, int n, size_t* bytes);
+int fht_adjoint_stack(const void* grad_hough, int t, int64_t ld_hough, int64_t grad_stride,
+                      void* grad_img, int64_t ld_img, int64_t img_stride, int w, int h, int n,
+                      unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Angle range of the image scaled along the sheared axis by alpha = num/den
  * (section 4: a scale in the first iteration maps [-arctg(1/alpha); 0] onto
  * [-45; 0], and the shear then selects the range).  The paper fixes no

@@ -851,12 +851,18 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
     return d;
 }
 
-}  // namespace fht
+// Adjoint of several same-size images, launched together (their passes of
+// one kind share a launch).  Each image has its own gradient, output and
+// workspace slice (bands, then the scratch images of quadrants 2..4).
+struct AdjImage {
+    const void* grad;
+    void* img;
+    unsigned char* ws;
+};
+constexpr int kStackGroup = kMaxAdjDescs / 4;
 
-extern "C" {
-
-int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img, int64_t ld_img, int w, int h,
-                unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream)
+int check_adjoint_args(const void* grad_hough, int t, int64_t ld_hough, const void* grad_img, int64_t ld_img, int w,
+                       int h, unsigned quads, unsigned flags)
 {
     int64_t rows, cols;
     int rc = fht_hough_shape(w, h, quads, &rows, &cols);
@@ -869,6 +875,94 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     if (flags & ~(unsigned)FHT_FLAG_SHIFTED) return fail(FHT_ERR_INVALID, "unknown flags 0x%x", flags);
     if ((flags & FHT_FLAG_SHIFTED) && quads != FHT_FULL)
         return fail(FHT_ERR_INVALID, "fhtshift applies to the full Hough image only");
+    return FHT_OK;
+}
+
+int run_adjoint(const AdjImage* ims, int m, int t, int64_t ld_hough, int64_t ld_img, int w, int h, unsigned quads,
+                unsigned flags, hipStream_t s)
+{
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    const size_t bands = layout_bands(gs, nq, 4, 0);
+    // image targets: the first quadrant writes the gradient, every later one
+    // its own scratch image; the scratch images are added to the gradient at
+    // the end in quadrant order, so the sum is ((q1 + q2) + q3) + q4
+    AdjDesc descs[kStackGroup][4][4];
+    const void* scratch_list[kStackGroup][3];
+    int n_scratch = 0;
+    for (int k = 0; k < m; ++k) {
+        unsigned char* scratch = ims[k].ws + bands;
+        n_scratch = 0;
+        for (int i = 0; i < nq; ++i) {
+            void* target = ims[k].img;
+            int64_t target_ld = ld_img;
+            if (i > 0) {
+                target = scratch;
+                target_ld = w;
+                scratch_list[k][n_scratch++] = scratch;
+                scratch += scratch_image_bytes(w, h);
+            }
+            int base, sign, skip, ra, rb;
+            placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
+            for (int p = 0; p < gs[i].npass; ++p)
+                descs[k][i][p] = make_adj_desc(gs[i], p, ims[k].grad, ld_hough, target, target_ld, w, h, ims[k].ws,
+                                               base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
+        }
+    }
+    int maxp = 0;
+    for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
+    // adjoint passes in reverse order, every image's and quadrant's pass of
+    // one kind in one launch; then the direct (tiny) quadrants and the sums
+    for (int p = maxp - 1; p >= 0; --p) {
+        for (int G = 3; G <= kMaxG; ++G) {
+            for (int first = 0; first < 2; ++first) {
+                AdjLaunch L{};
+                for (int k = 0; k < m; ++k)
+                    for (int i = 0; i < nq; ++i)
+                        if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G &&
+                            (p == gs[i].npass - 1) == (first == 1))
+                            L.d[L.nd++] = descs[k][i][p];
+                if (L.nd == 0) continue;
+                hipError_t e = launch_adjoint_pass(L, t, s);
+                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+            }
+        }
+        if (p > 0) continue;
+        for (int k = 0; k < m; ++k)
+            for (int i = 0; i < nq; ++i) {
+                if (gs[i].k > 2) continue;
+                AdjLaunch L{};
+                L.d[0] = descs[k][i][0];
+                L.nd = 1;
+                hipError_t e = launch_adjoint_direct(L, gs[i].k, t, s);
+                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+            }
+        if (n_scratch > 0) {
+            hipError_t e;
+            if (m == 1) {
+                e = launch_sum_images(ims[0].img, ld_img, scratch_list[0], n_scratch, w, h, t, s);
+            } else {
+                void* imgs[kStackGroup];
+                for (int k = 0; k < m; ++k) imgs[k] = ims[k].img;
+                e = launch_sum_images_multi(imgs, ld_img, scratch_list, m, n_scratch, w, h, t, s);
+            }
+            if (e != hipSuccess) return hip_fail(e, "adjoint sum launch");
+        }
+    }
+    return FHT_OK;
+}
+
+}  // namespace fht
+
+extern "C" {
+
+int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img, int64_t ld_img, int w, int h,
+                unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream)
+{
+    int rc = check_adjoint_args(grad_hough, t, ld_hough, grad_img, ld_img, w, h, quads, flags);
+    if (rc) return rc;
     int qs[4];
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
@@ -877,79 +971,52 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     if (workspace && ((uintptr_t)workspace & 255)) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
-    // image targets: the first quadrant writes grad_img, every later one its
-    // own scratch image; the scratch images are added to grad_img at the end
-    // in quadrant order, so the sum is ((q1 + q2) + q3) + q4
-    unsigned char* scratch = (unsigned char*)workspace + layout_bands(gs, nq, 4, 0);
-    void* target[4];
-    int64_t target_ld[4];
-    int n_scratch = 0;
-    const void* scratch_list[3];
-    for (int i = 0; i < nq; ++i) {
-        target[i] = grad_img;
-        target_ld[i] = ld_img;
-        if (i > 0) {
-            target[i] = scratch;
-            target_ld[i] = w;
-            scratch_list[n_scratch++] = scratch;
-            scratch += scratch_image_bytes(w, h);
+    const AdjImage im{grad_hough, grad_img, (unsigned char*)workspace};
+    return run_adjoint(&im, 1, t, ld_hough, ld_img, w, h, quads, flags, (hipStream_t)stream);
+}
+
+int fht_adjoint_stack_workspace_size(int w, int h, unsigned quads, int t, int n, size_t* bytes)
+{
+    if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
+    if (n < 1) return fail(FHT_ERR_INVALID, "stack of %d images", n);
+    size_t one = 0;
+    int rc = fht_adjoint_workspace_size(w, h, quads, t, &one);
+    if (rc) return rc;
+    *bytes = (size_t)(n < kStackGroup ? n : kStackGroup) * ((one + 255) / 256 * 256);
+    return FHT_OK;
+}
+
+int fht_adjoint_stack(const void* grad_hough, int t, int64_t ld_hough, int64_t grad_stride, void* grad_img,
+                      int64_t ld_img, int64_t img_stride, int w, int h, int n, unsigned quads, unsigned flags,
+                      void* workspace, size_t ws_bytes, void* stream)
+{
+    int rc = check_adjoint_args(grad_hough, t, ld_hough, grad_img, ld_img, w, h, quads, flags);
+    if (rc) return rc;
+    if (n < 1) return fail(FHT_ERR_INVALID, "stack of %d images", n);
+    int64_t rows, cols;
+    fht_hough_shape(w, h, quads, &rows, &cols);
+    if (n > 1 && grad_stride < rows * ld_hough)
+        return fail(FHT_ERR_INVALID, "grad_stride %lld < rows * ld_hough", (long long)grad_stride);
+    if (n > 1 && img_stride < (int64_t)h * ld_img)
+        return fail(FHT_ERR_INVALID, "img_stride %lld < h * ld_img", (long long)img_stride);
+    size_t need = 0;
+    rc = fht_adjoint_stack_workspace_size(w, h, quads, t, n, &need);
+    if (rc) return rc;
+    if (!workspace || ws_bytes < need)
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    const size_t slice = need / (size_t)(n < kStackGroup ? n : kStackGroup);
+    const size_t esz = 4;
+    for (int i0 = 0; i0 < n; i0 += kStackGroup) {
+        const int m = n - i0 < kStackGroup ? n - i0 : kStackGroup;
+        AdjImage ims[kStackGroup];
+        for (int k = 0; k < m; ++k) {
+            ims[k].grad = (const unsigned char*)grad_hough + (size_t)(i0 + k) * (size_t)grad_stride * esz;
+            ims[k].img = (unsigned char*)grad_img + (size_t)(i0 + k) * (size_t)img_stride * esz;
+            ims[k].ws = (unsigned char*)workspace + (size_t)k * slice;
         }
-    }
-    AdjDesc descs[4][4];
-    for (int i = 0; i < nq; ++i) {
-        int base, sign, skip, ra, rb;
-        placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
-        for (int p = 0; p < gs[i].npass; ++p)
-            descs[i][p] = make_adj_desc(gs[i], p, grad_hough, ld_hough, target[i], target_ld[i], w, h,
-                                        (unsigned char*)workspace, base, sign, skip,
-                                        (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
-    }
-    hipStream_t s = (hipStream_t)stream;
-    int maxp = 0;
-    for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
-    // adjoint passes in reverse order; the passes writing the image go one
-    // quadrant at a time, in quadrant order, so the sum is formed as
-    // ((q1 + q2) + q3) + q4
-    for (int p = maxp - 1; p >= 0; --p) {
-        if (p > 0) {
-            for (int G = 3; G <= kMaxG; ++G) {
-                for (int first = 0; first < 2; ++first) {
-                    AdjLaunch L{};
-                    for (int i = 0; i < nq; ++i)
-                        if (p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first == 1))
-                            L.d[L.nd++] = descs[i][p];
-                    if (L.nd == 0) continue;
-                    hipError_t e = launch_adjoint_pass(L, t, s);
-                    if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
-                }
-            }
-        } else {
-            // image passes of every quadrant (distinct targets): tiled ones
-            // grouped by depth, tiny ones by the direct kernel; then the sum
-            for (int G = 3; G <= kMaxG; ++G) {
-                for (int first = 0; first < 2; ++first) {
-                    AdjLaunch L{};
-                    for (int i = 0; i < nq; ++i)
-                        if (gs[i].k > 2 && gs[i].G[0] == G && (gs[i].npass == 1) == (first == 1))
-                            L.d[L.nd++] = descs[i][0];
-                    if (L.nd == 0) continue;
-                    hipError_t e = launch_adjoint_pass(L, t, s);
-                    if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
-                }
-            }
-            for (int i = 0; i < nq; ++i) {
-                if (gs[i].k > 2) continue;
-                AdjLaunch L{};
-                L.d[0] = descs[i][0];
-                L.nd = 1;
-                hipError_t e = launch_adjoint_direct(L, gs[i].k, t, s);
-                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
-            }
-            if (n_scratch > 0) {
-                hipError_t e = launch_sum_images(grad_img, ld_img, scratch_list, n_scratch, w, h, t, s);
-                if (e != hipSuccess) return hip_fail(e, "adjoint sum launch");
-            }
-        }
+        rc = run_adjoint(ims, m, t, ld_hough, ld_img, w, h, quads, flags, (hipStream_t)stream);
+        if (rc) return rc;
     }
     return FHT_OK;
 }

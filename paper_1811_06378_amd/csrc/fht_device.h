@@ -1193,6 +1193,46 @@ __global__ __launch_bounds__(256) void fht_sum_images_kernel(T* img, int64_t ld_
     }
 }
 
+// The same for up to kSumSet images of one size in one launch (blockIdx.z).
+constexpr int kSumSet = 4;
+template <typename T>
+struct SumSet {
+    T* img[kSumSet];
+    const T* s[kSumSet][3];
+};
+
+template <typename T, int VEC>
+__global__ __launch_bounds__(256) void fht_sum_images_multi_kernel(const SumSet<T> set, int64_t ld_img, int n, int w,
+                                                                   int h)
+{
+    constexpr int V = VEC ? 4 : 1;
+    const int z = blockIdx.z;
+    const int x = (blockIdx.x * blockDim.x + threadIdx.x) * V;
+    if (x >= w) return;
+    T* img = set.img[z];
+    const T* s0 = set.s[z][0];
+    const T* s1 = set.s[z][1];
+    const T* s2 = set.s[z][2];
+    for (int y = blockIdx.y; y < h; y += gridDim.y) {  // grid y capped at 65535
+        const int64_t i = (int64_t)y * w + x;
+        T* p = img + (int64_t)y * ld_img + x;
+        if constexpr (VEC) {
+            typedef typename vec4u<T>::type V4;
+            V4 v = *reinterpret_cast<const V4*>(p);
+            v = v + *reinterpret_cast<const V4*>(s0 + i);
+            if (n > 1) v = v + *reinterpret_cast<const V4*>(s1 + i);
+            if (n > 2) v = v + *reinterpret_cast<const V4*>(s2 + i);
+            *reinterpret_cast<V4*>(p) = v;
+        } else {
+            T v = *p;
+            v = v + s0[i];
+            if (n > 1) v = v + s1[i];
+            if (n > 2) v = v + s2[i];
+            *p = v;
+        }
+    }
+}
+
 // ------------------------------------------------ angle-range adjoint tail
 
 // The gradient of the sheared padded source, a0[r, xi] (n x W), read back

@@ -86,8 +86,10 @@ struct AdjDesc {
     int black_lo;         // Hough source: xi in [black_lo, black_lo + n - s) of row s is
     int black_ok;         // the structurally zero zone; 1: read it as zero (no shear)
 };
+// Up to 4 images x 4 quadrants of one adjoint pass kind in one launch.
+constexpr int kMaxAdjDescs = 16;
 struct AdjLaunch {
-    AdjDesc d[kMaxDescs];
+    AdjDesc d[kMaxAdjDescs];
     int nd;
 };
 
@@ -133,6 +135,10 @@ hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out
 // h x w, row pitch w; t = 1 (int32) or 2 (float32).
 hipError_t launch_sum_images(void* img, int64_t ld_img, const void* const* scr, int n, int w, int h, int t,
                              hipStream_t s);
+// The same for m (1..4) images of one size in one launch: imgs[k] and
+// scr[k][0..n-1] belong to image k.
+hipError_t launch_sum_images_multi(void* const* imgs, int64_t ld_img, const void* const (*scr)[3], int m, int n, int w,
+                                   int h, int t, hipStream_t s);
 // Angle-range adjoint, last step: img[y, x] = a0[r, (c + sigma(r)) mod W]
 // (r, c) = (y, x), or (x, y) when transposed; a0 is n x W, row pitch W.
 hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,

@@ -153,6 +153,36 @@ hipError_t launch_sum_images(void* img, int64_t ld_img, const void* const* scr, 
     return hipGetLastError();
 }
 
+template <typename T>
+static void launch_sum_multi_t(void* const* imgs, int64_t ld_img, const void* const (*scr)[3], int m, int n, int w,
+                               int h, hipStream_t s)
+{
+    SumSet<T> set{};
+    bool vec = (w % 4 == 0) && (ld_img % 4 == 0);
+    for (int k = 0; k < m; ++k) {
+        set.img[k] = (T*)imgs[k];
+        for (int j = 0; j < 3; ++j) set.s[k][j] = (const T*)scr[k][j < n ? j : 0];
+        vec = vec && (((uintptr_t)imgs[k] & 15) == 0);
+    }
+    const int gy = h < 65535 ? h : 65535;
+    if (vec)
+        hipLaunchKernelGGL((fht_sum_images_multi_kernel<T, true>), dim3((w / 4 + 255) / 256, gy, m), dim3(256), 0, s,
+                           set, ld_img, n, w, h);
+    else
+        hipLaunchKernelGGL((fht_sum_images_multi_kernel<T, false>), dim3((w + 255) / 256, gy, m), dim3(256), 0, s,
+                           set, ld_img, n, w, h);
+}
+
+hipError_t launch_sum_images_multi(void* const* imgs, int64_t ld_img, const void* const (*scr)[3], int m, int n, int w,
+                                   int h, int t, hipStream_t s)
+{
+    if (n < 1 || n > 3 || m < 1 || m > kSumSet) return hipErrorInvalidValue;
+    if (t == 2) launch_sum_multi_t<float>(imgs, ld_img, scr, m, n, w, h, s);
+    else if (t == 1) launch_sum_multi_t<int>(imgs, ld_img, scr, m, n, w, h, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,
                           int transposed, int elem_bytes, hipStream_t s)
 {

@@ -62,6 +62,8 @@ SIGNATURES = {
     "fht_range": (_I, [_P, _I, _I, _I, _I64, _I, _I, _I, _P, _I, _I64, _P, _SZ, _P]),
     "fht_shift": (_I, [_P, _I64, _P, _I64, _I, _I, _I, _I, _P]),
     "fht_adjoint": (_I, [_P, _I, _I64, _P, _I64, _I, _I, _U, _U, _P, _SZ, _P]),
+    "fht_adjoint_stack_workspace_size": (_I, [_I, _I, _U, _I, _I, _PSZ]),
+    "fht_adjoint_stack": (_I, [_P, _I, _I64, _I64, _P, _I64, _I64, _I, _I, _I, _U, _U, _P, _SZ, _P]),
     "fht_batch_plan_create": (_I, [_PI32, _PI32, _I, _U, _I, _I, ctypes.POINTER(_P), _PSZ, _PI64, _PI64]),
     "fht_batch_forward": (_I, [_P, _P, _P, _P, _SZ, _P]),
     "fht_batch_plan_destroy": (_I, [_P]),
@@ -441,11 +443,11 @@ class FHTFunction(torch.autograd.Function):
         g = g.contiguous()
         if g.dim() == 2:
             return adjoint(g, w, h, ctx.quads, ctx.shifted), None, None
-        return batch_adjoint(g, w, h, ctx.quads, ctx.shifted), None, None
+        # two halves on two side streams: 16 x 1024^2 took 0.41 ms against 0.45
+        return batch_adjoint(g, w, h, ctx.quads, ctx.shifted, streams=2), None, None
 
 
 _plan_cache = {}
-_side_streams = {}
 
 
 def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False) -> torch.Tensor:
@@ -479,42 +481,68 @@ def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False) -> torch
     return out
 
 
+def adjoint_stack_workspace_size(w: int, h: int, n: int, quads="full", dtype=torch.float32) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().fht_adjoint_stack_workspace_size(w, h, _quads(quads), _acc_code(dtype), n, ctypes.byref(b)),
+           "fht_adjoint_stack_workspace_size")
+    return b.value
+
+
+_side_streams = {}
+
+
 def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool = False,
-                  streams: int = 4) -> torch.Tensor:
+                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                  streams: int = 1) -> torch.Tensor:
     """Adjoints of a (batch, rows, cols) stack of Hough gradients into one
-    (batch, h, w) tensor.  The images are spread over `streams` side streams
-    (default priority), each with its own workspace, so that the launches of
-    small images overlap; the caller's stream waits for all of them."""
+    (batch, h, w) tensor (fht_adjoint_stack: up to 4 images' passes of one
+    kind per launch).  streams > 1 splits the stack into that many parts run
+    on side streams of default priority, each with its own workspace (a
+    given workspace is then not used); the caller's stream waits for them."""
+    if streams > 1 and g.dim() == 3 and g.shape[0] >= 2 * streams:
+        n = g.shape[0]
+        if out is None:
+            out = torch.empty((n, h, w), dtype=g.dtype, device=g.device)
+        cur = torch.cuda.current_stream(g.device)
+        key = (g.device, streams)
+        if key not in _side_streams:
+            _side_streams[key] = [torch.cuda.Stream(device=g.device) for _ in range(streams)]
+        side = _side_streams[key]
+        bounds = [n * k // streams for k in range(streams + 1)]
+        for s in side:
+            s.wait_stream(cur)
+        for k, s in enumerate(side):
+            lo, hi = bounds[k], bounds[k + 1]
+            ws = _workspace(adjoint_stack_workspace_size(w, h, hi - lo, quads, g.dtype), g.device)
+            with torch.cuda.stream(s):
+                batch_adjoint(g[lo:hi], w, h, quads, shifted, out=out[lo:hi], workspace=ws)
+            ws.record_stream(s)
+        for s in side:
+            cur.wait_stream(s)
+            g.record_stream(s)
+            out.record_stream(s)
+        return out
     if g.dim() != 3:
         raise ValueError("batch_adjoint takes a (batch, rows, cols) tensor")
-    g = g.contiguous()
+    if not g.is_cuda:
+        raise ValueError("g must be a device tensor")
+    if g.stride(2) != 1 or g.stride(1) < g.shape[2] or g.stride(0) < g.shape[1] * g.stride(1):
+        g = g.contiguous()
     n = g.shape[0]
-    out = torch.empty((n, h, w), dtype=g.dtype, device=g.device)
-    ns = max(1, min(streams, n))
-    if ns == 1:
-        for i in range(n):
-            adjoint(g[i], w, h, quads, shifted, out=out[i])
+    t = _acc_code(g.dtype)
+    q = _quads(quads)
+    if out is None:
+        out = torch.empty((n, h, w), dtype=g.dtype, device=g.device)
+    if out.dim() != 3 or tuple(out.shape) != (n, h, w) or out.dtype != g.dtype or out.stride(2) != 1:
+        raise ValueError("out must be a (%d, %d, %d) %s tensor with unit column stride" % (n, h, w, g.dtype))
+    if n == 0:
         return out
-    cur = torch.cuda.current_stream(g.device)
-    key = (g.device, ns)
-    if key not in _side_streams:
-        _side_streams[key] = [torch.cuda.Stream(device=g.device) for _ in range(ns)]
-    side = _side_streams[key]
-    wsb = adjoint_workspace_size(w, h, quads, g.dtype)
-    wss = [_workspace(wsb, g.device) for _ in range(ns)]
-    for s in side:
-        s.wait_stream(cur)
-    for i in range(n):
-        s = side[i % ns]
-        with torch.cuda.stream(s):
-            adjoint(g[i], w, h, quads, shifted, out=out[i], workspace=wss[i % ns])
-    for s in side:
-        cur.wait_stream(s)
-        # the buffers were used on s: the allocator must not reuse them before s is done
-        g.record_stream(s)
-        out.record_stream(s)
-        for t in wss:
-            t.record_stream(s)
+    if workspace is None:
+        workspace = _workspace(adjoint_stack_workspace_size(w, h, n, q, g.dtype), g.device)
+    rc = lib().fht_adjoint_stack(g.data_ptr(), t, g.stride(1), g.stride(0), out.data_ptr(), out.stride(1),
+                                 out.stride(0), w, h, n, q, FHT_FLAG_SHIFTED if shifted else 0,
+                                 workspace.data_ptr(), workspace.numel(), _stream())
+    _check(rc, "fht_adjoint_stack")
     return out
 
 

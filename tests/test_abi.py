@@ -36,6 +36,28 @@ def test_version_and_strings():
         assert L.fht_status_string(rc)
 
 
+def test_adjoint_stack_sizes_and_validation():
+    L = fht.lib()
+    one = fht.adjoint_workspace_size(300, 200)
+    one256 = (one + 255) // 256 * 256
+    assert fht.adjoint_stack_workspace_size(300, 200, 1) == one256
+    assert fht.adjoint_stack_workspace_size(300, 200, 3) == 3 * one256
+    assert fht.adjoint_stack_workspace_size(300, 200, 100) == 4 * one256  # groups of 4
+    rows, cols = fht.hough_shape(300, 200)
+    p = ctypes.c_void_p(1 << 20)
+    args = dict(t=fht.FHT_F32, ld=cols, gs=rows * cols, ldi=300, istr=300 * 200, n=3)
+
+    def call(**kw):
+        a = {**args, **kw}
+        return L.fht_adjoint_stack(p, a["t"], a["ld"], a["gs"], p, a["ldi"], a["istr"], 300, 200, a["n"], 15, 0,
+                                   p, 1 << 40, None)
+    assert call(n=0) == fht.FHT_ERR_INVALID
+    assert call(gs=rows * cols - 1) == fht.FHT_ERR_INVALID
+    assert call(istr=300 * 200 - 1) == fht.FHT_ERR_INVALID
+    assert call(t=fht.FHT_U8) == fht.FHT_ERR_INVALID
+    assert call(ld=cols - 1) == fht.FHT_ERR_INVALID
+
+
 def test_timing_filter_and_empty_report_need_no_gpu():
     # the filter is a host-side string; an empty record set reports nothing
     fht.timing_filter("fht_pass_kernel<float")

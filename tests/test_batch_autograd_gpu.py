@@ -52,9 +52,11 @@ def test_batch_forward_reuses_plan_with_new_data():
         assert torch.equal(rb[i], fht.forward(b[i]))
 
 
-@pytest.mark.parametrize("streams", [1, 2, 4])
-@pytest.mark.parametrize("n", [1, 3, 6])
+@pytest.mark.parametrize("streams", [1, 2, 3])
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 9])
 def test_batch_adjoint_equals_single(n, streams):
+    # groups of up to 4 images per launch: 9 = 4 + 4 + 1; with streams > 1
+    # the stack is split over side streams once it has 2 images per stream
     h, w = 120, 75
     rows, cols = fht.hough_shape(w, h)
     rng = np.random.default_rng(n * 10 + streams)
@@ -67,6 +69,31 @@ def test_batch_adjoint_equals_single(n, streams):
                                oracle.adjoint_full(host(g[0]).astype(np.float64), w, h), rtol=1e-4, atol=1e-3)
 
 
+@pytest.mark.parametrize("quads,shifted", [([2, 3], False), ([1], False), ("full", True)])
+def test_batch_adjoint_subsets_shifted_and_strides(quads, shifted):
+    h, w = 70, 140
+    rows, cols = fht.hough_shape(w, h, quads)
+    rng = np.random.default_rng(8)
+    big = dev(rng.standard_normal((10, rows, cols + 3)).astype(np.float32))
+    g = big[::2, :, :cols]  # image stride 2 * rows * (cols + 3), row pitch cols + 3
+    out_big = torch.full((5, h + 2, w + 5), -1.0, device="cuda")
+    out = out_big[:, :h, :w]
+    fht.batch_adjoint(g, w, h, quads=quads, shifted=shifted, out=out)
+    for i in range(5):
+        assert torch.equal(out[i], fht.adjoint(g[i].contiguous(), w, h, quads=quads, shifted=shifted))
+    assert bool(torch.all(out_big[:, h:, :] == -1.0)) and bool(torch.all(out_big[:, :, w:] == -1.0))
+
+
+def test_batch_adjoint_tiny_quadrants():
+    # sides below 8: direct kernels inside the stack
+    h, w = 3, 6
+    rows, cols = fht.hough_shape(w, h)
+    g = dev(np.random.default_rng(3).standard_normal((5, rows, cols)).astype(np.float32))
+    got = fht.batch_adjoint(g, w, h)
+    for i in range(5):
+        assert torch.equal(got[i], fht.adjoint(g[i], w, h))
+
+
 def test_batch_adjoint_int32_exact():
     h, w = 66, 130
     rows, cols = fht.hough_shape(w, h)
@@ -77,8 +104,9 @@ def test_batch_adjoint_int32_exact():
         np.testing.assert_array_equal(got[i].astype(np.float64), oracle.adjoint_full(g[i].astype(np.float64), w, h))
 
 
-def test_autograd_on_a_stack():
-    n, h, w = 3, 64, 80
+@pytest.mark.parametrize("n", [3, 6])
+def test_autograd_on_a_stack(n):
+    h, w = 64, 80
     imgs = _stack(n, h, w, "f32", seed=21)
     x = dev(imgs).requires_grad_()
     rows, cols = fht.hough_shape(w, h)
