@@ -490,6 +490,7 @@ def adjoint_stack_workspace_size(w: int, h: int, n: int, quads="full", dtype=tor
 
 
 _side_streams = {}
+_side_workspaces = {}  # (device, streams, index) -> workspace used only on that side stream
 
 
 def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool = False,
@@ -514,10 +515,18 @@ def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool =
             s.wait_stream(cur)
         for k, s in enumerate(side):
             lo, hi = bounds[k], bounds[k + 1]
-            ws = _workspace(adjoint_stack_workspace_size(w, h, hi - lo, quads, g.dtype), g.device)
+            # one workspace per side stream, kept between calls: work on one
+            # stream runs in order, so reusing it is safe, and the allocator
+            # is not asked for a block that a pending stream still holds
+            need = adjoint_stack_workspace_size(w, h, hi - lo, quads, g.dtype)
+            wkey = (g.device, streams, k)
+            ws = _side_workspaces.get(wkey)
+            if ws is None or ws.numel() < need:
+                with torch.cuda.stream(s):
+                    ws = _workspace(need, g.device)
+                _side_workspaces[wkey] = ws
             with torch.cuda.stream(s):
                 batch_adjoint(g[lo:hi], w, h, quads, shifted, out=out[lo:hi], workspace=ws)
-            ws.record_stream(s)
         for s in side:
             cur.wait_stream(s)
             g.record_stream(s)
