@@ -183,7 +183,9 @@ def pass_split(side: int):
 
 
 def set_pass_split(k: int, passes=None):
-    """Stage split for quadrants of 2^k rows (None restores the default)."""
+    """Stage split for quadrants of 2^k rows (None restores the default).
+    Cached stack plans are dropped, so later stacks are planned with it."""
+    _plan_cache.clear()
     if passes is None:
         _check(lib().fht_set_pass_split(k, 0, None), "fht_set_pass_split")
         return
@@ -197,6 +199,7 @@ def autotune(w: int, h: int, in_dtype=torch.float32, reps: int = 20):
     now used for both sides."""
     it, at, _ = _dtypes(in_dtype)
     _check(lib().fht_autotune(w, h, it, at, reps, _stream()), "fht_autotune")
+    _plan_cache.clear()
     return pass_split(h), pass_split(w)
 
 
