@@ -30,3 +30,4 @@ from .oracle import (  # noqa: F401
     range_scaled,
     scaled_sizes,
 )
+from . import lines  # noqa: F401,E402

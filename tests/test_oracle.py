@@ -55,6 +55,44 @@ def test_quadrant_matches_brute_force(oracle_mod, h, w, q):
     np.testing.assert_array_equal(oracle_mod.quadrant(img, q), bf.quadrant(img, q))
 
 
+# The single-cell routines are the checker wherever the whole oracle is too
+# slow (the 65536 side) and the sampled checks beside the whole-image
+# comparisons, so they are pinned on their own: every (row, x0) of small
+# non-square images, every quadrant, against brute force along the
+# explicitly built pattern (section 2 pattern sums; section 3.3 row order).
+CELL_SIZES = [(3, 5), (5, 3), (7, 12), (12, 7), (16, 9), (9, 30), (2, 13), (1, 6)]
+
+
+@pytest.mark.parametrize("h,w", CELL_SIZES)
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_cell_matches_brute_force_everywhere(oracle_mod, h, w, q):
+    img = _rand(h, w, seed=40 + q, lo=-7, hi=9)
+    want = bf.quadrant(img, q)
+    n, W = want.shape
+    got = np.array([[oracle_mod.cell(img, q, s, x) for x in range(W)] for s in range(n)])
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("h,w", CELL_SIZES)
+def test_full_cells_match_brute_force_everywhere(oracle_mod, h, w):
+    img = _rand(h, w, seed=50, lo=-7, hi=9)
+    want = bf.full(img)
+    rows, W = want.shape
+    rr, cc = np.meshgrid(np.arange(rows), np.arange(W), indexing="ij")
+    got = oracle_mod.full_cells(img, rr.ravel(), cc.ravel()).reshape(rows, W)
+    np.testing.assert_array_equal(got, want)
+    # and one by one, the scalar entry point
+    for r in range(rows):
+        assert oracle_mod.full_cell(img, r, (3 * r + 1) % W) == want[r, (3 * r + 1) % W]
+
+
+def test_full_cell_outside_the_image_is_nan(oracle_mod):
+    img = _rand(5, 7)
+    rows, W = oracle_mod.hough_shape(7, 5)
+    assert math.isnan(oracle_mod.full_cell(img, rows, 0))
+    assert math.isnan(oracle_mod.full_cell(img, -1, 0))
+
+
 @pytest.mark.parametrize("h,w", [(8, 8), (5, 12), (16, 3)])
 def test_full_matches_brute_force(oracle_mod, h, w):
     img = _rand(h, w, seed=7)
