@@ -150,11 +150,33 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _check_2d(x: torch.Tensor, name: str):
-    if not x.is_cuda:
-        raise ValueError("%s must be a device tensor" % name)
-    if x.dim() != 2 or x.stride(1) != 1:
-        raise ValueError("%s must be 2-D with unit column stride" % name)
+def _check_2d(x: torch.Tensor, name: str, shape=None, dtype=None):
+    """The C entry points see only pointers and pitches, so the extent every
+    kernel reads or writes is checked here: 2-D, unit column stride, a row
+    pitch covering a row, and (when given) the exact shape and dtype.  The
+    device is checked last, so a mis-shaped tensor is reported as such."""
+    if x.dim() != 2 or x.stride(1) != 1 or (x.shape[0] > 1 and x.stride(0) < x.shape[1]):
+        raise ValueError("%s must be 2-D with unit column stride and a row pitch >= its width" % name)
+    if shape is not None and tuple(x.shape) != tuple(int(v) for v in shape):
+        raise ValueError("%s must be %dx%d, got %dx%d" % (name, shape[0], shape[1], x.shape[0], x.shape[1]))
+    if dtype is not None and x.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, x.dtype))
+
+
+def _check_device(**tensors):
+    """Last check before a call into the library: every tensor on a GPU."""
+    for name, x in tensors.items():
+        if not x.is_cuda:
+            raise ValueError("%s must be a device tensor" % name)
+
+
+def _check_workspace(ws: torch.Tensor, need: int, name: str = "workspace"):
+    if ws.dtype != torch.uint8 or ws.dim() != 1 or not ws.is_contiguous():
+        raise ValueError("%s must be a contiguous 1-D uint8 tensor" % name)
+    if ws.numel() < need:
+        raise ValueError("%s holds %d bytes, %d needed" % (name, ws.numel(), need))
+    if ws.data_ptr() % 256:
+        raise ValueError("%s must be 256-byte aligned" % name)
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
@@ -224,13 +246,13 @@ def forward(img: torch.Tensor, quads="full", shifted: bool = False, out: torch.T
     rows, cols = hough_shape(w, h, q)
     if out is None:
         out = torch.empty((rows, cols), dtype=odt, device=img.device)
-    _check_2d(out, "out")
-    if out.shape[0] != rows or out.shape[1] != cols or out.dtype != odt:
-        raise ValueError("out must be %dx%d %s" % (rows, cols, odt))
+    _check_2d(out, "out", (rows, cols), odt)
     nb = workspace_size(w, h, q, img.dtype)
     if workspace is None:
         workspace = _workspace(nb, img.device)
+    _check_workspace(workspace, nb)
     flags = (FHT_FLAG_SHIFTED if shifted else 0) | (FHT_FLAG_MAX if op == "max" else 0)
+    _check_device(img=img, out=out, workspace=workspace)
     rc = lib().fht_forward(img.data_ptr(), it, w, h, img.stride(0), out.data_ptr(), at, out.stride(0), q,
                            flags, workspace.data_ptr(),
                            workspace.numel() * workspace.element_size(), _stream())
@@ -251,8 +273,17 @@ def range_params(n: int, deg_lo: float, deg_hi: float):
     return int(S1), int(S)
 
 
+def range_workspace_size(w: int, h: int, S1: int, S: int, transposed: bool = False,
+                         in_dtype=torch.float32) -> int:
+    it, at, _ = _dtypes(in_dtype)
+    b = ctypes.c_size_t()
+    _check(lib().fht_range_workspace_size(w, h, S1, S, int(transposed), it, at, ctypes.byref(b)),
+           "fht_range_workspace_size")
+    return b.value
+
+
 def range_transform(img: torch.Tensor, S1: int, S: int, transposed: bool = False,
-                    out: torch.Tensor | None = None) -> torch.Tensor:
+                    out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Angle-range transform (section 4): (S+1) x W."""
     _check_2d(img, "img")
     h, w = img.shape
@@ -260,55 +291,75 @@ def range_transform(img: torch.Tensor, S1: int, S: int, transposed: bool = False
     rows, cols = range_shape(w, h, S1, S, transposed)
     if out is None:
         out = torch.empty((rows, cols), dtype=odt, device=img.device)
-    _check_2d(out, "out")
-    b = ctypes.c_size_t()
-    _check(lib().fht_range_workspace_size(w, h, S1, S, int(transposed), it, at, ctypes.byref(b)),
-           "fht_range_workspace_size")
-    ws = _workspace(b.value, img.device)
+    _check_2d(out, "out", (rows, cols), odt)
+    need = range_workspace_size(w, h, S1, S, transposed, img.dtype)
+    ws = _workspace(need, img.device) if workspace is None else workspace
+    _check_workspace(ws, need)
+    _check_device(img=img, out=out, workspace=ws)
     rc = lib().fht_range(img.data_ptr(), it, w, h, img.stride(0), S1, S, int(transposed), out.data_ptr(), at,
                          out.stride(0), ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "fht_range")
     return out
 
 
+def range_scaled_shape(w: int, h: int, num: int, den: int, S1: int, S: int, transposed: bool = False):
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fht_range_scaled_shape(w, h, num, den, S1, S, int(transposed), ctypes.byref(r), ctypes.byref(c)),
+           "fht_range_scaled_shape")
+    return r.value, c.value
+
+
+def range_scaled_workspace_size(w: int, h: int, num: int, den: int, S1: int, S: int, transposed: bool = False,
+                                in_dtype=torch.float32) -> int:
+    it, at, _ = _dtypes(in_dtype)
+    b = ctypes.c_size_t()
+    _check(lib().fht_range_scaled_workspace_size(w, h, num, den, S1, S, int(transposed), it, at, ctypes.byref(b)),
+           "fht_range_scaled_workspace_size")
+    return b.value
+
+
 def range_scaled(img: torch.Tensor, num: int, den: int, S1: int, S: int, transposed: bool = False,
-                 out: torch.Tensor | None = None) -> torch.Tensor:
+                 out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Angle range (section 4) of the image scaled by num/den along the
     sheared axis, nearest source sample (see include/fht.h)."""
     _check_2d(img, "img")
     h, w = img.shape
     it, at, odt = _dtypes(img.dtype)
-    r, c = ctypes.c_int64(), ctypes.c_int64()
-    _check(lib().fht_range_scaled_shape(w, h, num, den, S1, S, int(transposed), ctypes.byref(r), ctypes.byref(c)),
-           "fht_range_scaled_shape")
+    rows, cols = range_scaled_shape(w, h, num, den, S1, S, transposed)
     if out is None:
-        out = torch.empty((r.value, c.value), dtype=odt, device=img.device)
-    _check_2d(out, "out")
-    b = ctypes.c_size_t()
-    _check(lib().fht_range_scaled_workspace_size(w, h, num, den, S1, S, int(transposed), it, at, ctypes.byref(b)),
-           "fht_range_scaled_workspace_size")
-    ws = _workspace(b.value, img.device)
+        out = torch.empty((rows, cols), dtype=odt, device=img.device)
+    _check_2d(out, "out", (rows, cols), odt)
+    need = range_scaled_workspace_size(w, h, num, den, S1, S, transposed, img.dtype)
+    ws = _workspace(need, img.device) if workspace is None else workspace
+    _check_workspace(ws, need)
+    _check_device(img=img, out=out, workspace=ws)
     rc = lib().fht_range_scaled(img.data_ptr(), it, w, h, img.stride(0), num, den, S1, S, int(transposed),
                                 out.data_ptr(), at, out.stride(0), ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "fht_range_scaled")
     return out
 
 
+def range_adjoint_workspace_size(w: int, h: int, S1: int, S: int, transposed: bool = False,
+                                 dtype=torch.float32) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().fht_range_adjoint_workspace_size(w, h, S1, S, int(transposed), _acc_code(dtype), ctypes.byref(b)),
+           "fht_range_adjoint_workspace_size")
+    return b.value
+
+
 def range_adjoint(grad: torch.Tensor, w: int, h: int, S1: int, S: int, transposed: bool = False,
-                  out: torch.Tensor | None = None) -> torch.Tensor:
+                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Adjoint of range_transform: (S+1) x W gradient -> h x w image gradient."""
-    _check_2d(grad, "grad")
     t = _acc_code(grad.dtype)
     rows, cols = range_shape(w, h, S1, S, transposed)
-    if grad.shape[0] != rows or grad.shape[1] != cols:
-        raise ValueError("grad must be %dx%d" % (rows, cols))
+    _check_2d(grad, "grad", (rows, cols))
     if out is None:
         out = torch.empty((h, w), dtype=grad.dtype, device=grad.device)
-    _check_2d(out, "out")
-    b = ctypes.c_size_t()
-    _check(lib().fht_range_adjoint_workspace_size(w, h, S1, S, int(transposed), t, ctypes.byref(b)),
-           "fht_range_adjoint_workspace_size")
-    ws = _workspace(b.value, grad.device)
+    _check_2d(out, "out", (h, w), grad.dtype)
+    need = range_adjoint_workspace_size(w, h, S1, S, transposed, grad.dtype)
+    ws = _workspace(need, grad.device) if workspace is None else workspace
+    _check_workspace(ws, need)
+    _check_device(grad=grad, out=out, workspace=ws)
     rc = lib().fht_range_adjoint(grad.data_ptr(), t, grad.stride(0), S1, S, int(transposed), out.data_ptr(),
                                  out.stride(0), w, h, ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "fht_range_adjoint")
@@ -385,11 +436,13 @@ def range_degrees(img: torch.Tensor, deg_lo: float, deg_hi: float, transposed: b
 
 def shift(hough: torch.Tensor, w: int, h: int, inverse: bool = False, out: torch.Tensor | None = None):
     """fhtshift (section 5) of a full Hough image; out=hough rolls in place."""
-    _check_2d(hough, "hough")
     t = _acc_code(hough.dtype)
+    rows, cols = hough_shape(w, h)
+    _check_2d(hough, "hough", (rows, cols))
     if out is None:
         out = torch.empty_like(hough)
-    _check_2d(out, "out")
+    _check_2d(out, "out", (rows, cols), hough.dtype)
+    _check_device(hough=hough, out=out)
     rc = lib().fht_shift(hough.data_ptr(), hough.stride(0), out.data_ptr(), out.stride(0), t, w, h,
                          int(inverse), _stream())
     _check(rc, "fht_shift")
@@ -406,14 +459,17 @@ def adjoint_workspace_size(w: int, h: int, quads="full", dtype=torch.float32) ->
 def adjoint(grad: torch.Tensor, w: int, h: int, quads="full", shifted: bool = False,
             out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Transpose of forward: Hough-shaped gradient -> h x w image gradient."""
-    _check_2d(grad, "grad")
     t = _acc_code(grad.dtype)
     q = _quads(quads)
+    _check_2d(grad, "grad", hough_shape(w, h, q))
     if out is None:
         out = torch.empty((h, w), dtype=grad.dtype, device=grad.device)
-    _check_2d(out, "out")
+    _check_2d(out, "out", (h, w), grad.dtype)
+    need = adjoint_workspace_size(w, h, q, grad.dtype)
     if workspace is None:
-        workspace = _workspace(adjoint_workspace_size(w, h, q, grad.dtype), grad.device)
+        workspace = _workspace(need, grad.device)
+    _check_workspace(workspace, need)
+    _check_device(grad=grad, out=out, workspace=workspace)
     rc = lib().fht_adjoint(grad.data_ptr(), t, grad.stride(0), out.data_ptr(), out.stride(0), w, h, q,
                            FHT_FLAG_SHIFTED if shifted else 0, workspace.data_ptr(),
                            workspace.numel() * workspace.element_size(), _stream())
@@ -503,9 +559,24 @@ def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool =
     (batch, h, w) tensor (fht_adjoint_stack: up to 4 images' passes of one
     kind per launch).  streams > 1 splits the stack into that many parts run
     on side streams of default priority, each with its own workspace (a
-    given workspace is then not used); the caller's stream waits for them."""
-    if streams > 1 and g.dim() == 3 and g.shape[0] >= 2 * streams:
-        n = g.shape[0]
+    given workspace is then not used); the caller's stream waits for them.
+    Inside a stream capture the stack runs on the capturing stream with a
+    workspace of its own, so a captured graph never holds a block that later
+    eager calls reuse or release."""
+    q = _quads(quads)
+    rows, cols = hough_shape(w, h, q)
+    t = _acc_code(g.dtype)
+    if g.dim() != 3 or tuple(g.shape[1:]) != (rows, cols):
+        raise ValueError("g must be a (batch, %d, %d) tensor" % (rows, cols))
+    n = g.shape[0]
+    if out is not None and (out.dim() != 3 or tuple(out.shape) != (n, h, w) or out.dtype != g.dtype
+                            or out.stride(2) != 1 or (h > 1 and out.stride(1) < w)
+                            or (n > 1 and out.stride(0) < h * out.stride(1))):
+        raise ValueError("out must be a (%d, %d, %d) %s tensor with unit column stride" % (n, h, w, g.dtype))
+    if not g.is_cuda:
+        raise ValueError("g must be a device tensor")
+    capturing = torch.cuda.is_current_stream_capturing()
+    if streams > 1 and n >= 2 * streams and not capturing:
         if out is None:
             out = torch.empty((n, h, w), dtype=g.dtype, device=g.device)
         cur = torch.cuda.current_stream(g.device)
@@ -519,8 +590,9 @@ def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool =
         for k, s in enumerate(side):
             lo, hi = bounds[k], bounds[k + 1]
             # one workspace per side stream, kept between calls: work on one
-            # stream runs in order, so reusing it is safe, and the allocator
-            # is not asked for a block that a pending stream still holds
+            # stream runs in order, so reusing it is safe; a replaced block
+            # was allocated on that stream, so the allocator hands it out
+            # again only to later work of the same stream
             need = adjoint_stack_workspace_size(w, h, hi - lo, quads, g.dtype)
             wkey = (g.device, streams, k)
             ws = _side_workspaces.get(wkey)
@@ -535,23 +607,17 @@ def batch_adjoint(g: torch.Tensor, w: int, h: int, quads="full", shifted: bool =
             g.record_stream(s)
             out.record_stream(s)
         return out
-    if g.dim() != 3:
-        raise ValueError("batch_adjoint takes a (batch, rows, cols) tensor")
-    if not g.is_cuda:
-        raise ValueError("g must be a device tensor")
     if g.stride(2) != 1 or g.stride(1) < g.shape[2] or g.stride(0) < g.shape[1] * g.stride(1):
         g = g.contiguous()
-    n = g.shape[0]
-    t = _acc_code(g.dtype)
-    q = _quads(quads)
     if out is None:
         out = torch.empty((n, h, w), dtype=g.dtype, device=g.device)
-    if out.dim() != 3 or tuple(out.shape) != (n, h, w) or out.dtype != g.dtype or out.stride(2) != 1:
-        raise ValueError("out must be a (%d, %d, %d) %s tensor with unit column stride" % (n, h, w, g.dtype))
     if n == 0:
         return out
+    need = adjoint_stack_workspace_size(w, h, n, q, g.dtype)
     if workspace is None:
-        workspace = _workspace(adjoint_stack_workspace_size(w, h, n, q, g.dtype), g.device)
+        workspace = _workspace(need, g.device)
+    _check_workspace(workspace, need)
+    _check_device(g=g, out=out, workspace=workspace)
     rc = lib().fht_adjoint_stack(g.data_ptr(), t, g.stride(1), g.stride(0), out.data_ptr(), out.stride(1),
                                  out.stride(0), w, h, n, q, FHT_FLAG_SHIFTED if shifted else 0,
                                  workspace.data_ptr(), workspace.numel(), _stream())
@@ -573,24 +639,31 @@ def cell_segment(w: int, h: int, row: int, x0: int, quads="full", shifted: bool 
     return (seg[0], seg[1]), (seg[2], seg[3]), seg[4]
 
 
-def peaks(hough: torch.Tensor, radius: int = 4, threshold: float = 0.0, max_out: int = 4096):
+def peaks(hough: torch.Tensor, radius: int = 4, threshold: float = 0.0, max_out: int | None = None):
     """Local maxima of a Hough image: [(value, row, col)] by decreasing value
-    (ties by index), and the total number found (may exceed max_out)."""
+    (ties by index), and the total number found.  With max_out given, at most
+    that many (an arbitrary subset when more exist); with None, all of them
+    (a second launch when the first buffer was too small)."""
     _check_2d(hough, "hough")
     t = _acc_code(hough.dtype)
+    _check_device(hough=hough)
     rows, cols = hough.shape
-    out = torch.empty(max_out, dtype=torch.int64, device=hough.device)
-    count = torch.zeros(1, dtype=torch.int32, device=hough.device)
-    _check(lib().fht_peaks(hough.data_ptr(), t, rows, cols, hough.stride(0), radius, float(threshold),
-                           out.data_ptr(), max_out, count.data_ptr(), _stream()), "fht_peaks")
-    total = int(count.item())
-    idx = out[:min(total, max_out)].cpu().tolist()
+    cap = max_out if max_out is not None else 65536
+    while True:
+        out = torch.empty(cap, dtype=torch.int64, device=hough.device)
+        count = torch.zeros(1, dtype=torch.int32, device=hough.device)
+        _check(lib().fht_peaks(hough.data_ptr(), t, rows, cols, hough.stride(0), radius, float(threshold),
+                               out.data_ptr(), cap, count.data_ptr(), _stream()), "fht_peaks")
+        total = int(count.item())
+        if max_out is not None or total <= cap:
+            break
+        cap = total
+    idx = out[:min(total, cap)]
     res = []
-    if idx:
-        flat = torch.tensor(idx, dtype=torch.int64, device=hough.device)
-        rr, cc = flat // cols, flat % cols
+    if idx.numel():
+        rr, cc = idx // cols, idx % cols
         vals = hough[rr, cc].cpu().tolist()
-        res = sorted(((v, i // cols, i % cols) for v, i in zip(vals, idx)), key=lambda e: (-e[0], e[1], e[2]))
+        res = sorted(zip(vals, rr.cpu().tolist(), cc.cpu().tolist()), key=lambda e: (-e[0], e[1], e[2]))
     return res, total
 
 
@@ -668,6 +741,9 @@ class BatchPlan:
         return [packed[o:o + r * c].view(r, c) for o, (r, c) in zip(self.offsets, self.shapes)]
 
     def pointer_table(self, imgs) -> torch.Tensor:
+        imgs = list(imgs)
+        if len(imgs) != self.n:
+            raise ValueError("the plan holds %d images, %d given" % (self.n, len(imgs)))
         for x, (h, w) in zip(imgs, self.sizes):
             if x.shape != (h, w) or x.dtype != self.in_dtype or not x.is_contiguous() or x.device != self.device:
                 raise ValueError("batch image does not match the plan")
@@ -684,9 +760,17 @@ class BatchPlan:
         """One batched forward on the current stream.  A workspace passed in
         (at least workspace_bytes, 256-byte aligned) is used instead of the
         plan's own, so calls on different streams do not share one."""
+        if (ptr_table.dtype != torch.int64 or ptr_table.dim() != 1 or ptr_table.numel() != self.n
+                or not ptr_table.is_contiguous()):
+            raise ValueError("ptr_table must be a contiguous int64 tensor of %d pointers" % self.n)
+        if (packed.dtype != self.out_dtype or not packed.is_contiguous() or packed.numel() < self.out_elems):
+            raise ValueError("packed must be a contiguous %s tensor of at least %d elements"
+                             % (self.out_dtype, self.out_elems))
+        if ptr_table.device != self.device or packed.device != self.device:
+            raise ValueError("ptr_table and packed must be on the plan's device")
         ws = self.workspace if workspace is None else workspace
-        if ws.numel() < self.workspace_bytes:
-            raise ValueError("batch workspace too small")
+        _check_workspace(ws, self.workspace_bytes, "batch workspace")
+        _check_device(ptr_table=ptr_table, packed=packed, workspace=ws)
         rc = lib().fht_batch_forward(self._plan, ptr_table.data_ptr(), packed.data_ptr(), ws.data_ptr(), ws.numel(),
                                      _stream())
         _check(rc, "fht_batch_forward")

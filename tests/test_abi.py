@@ -209,3 +209,54 @@ def test_set_pass_split_validation_and_roundtrip():
     finally:
         fht.set_pass_split(10, None)
     assert fht.pass_split(1024) == [5, 5]
+
+
+# The C entry points see only pointers and pitches; the binding checks every
+# tensor's extent and dtype first.  CPU tensors suffice: a mis-shaped tensor
+# is rejected for its shape (the device check comes last), so no call
+# reaches the library's launch path.
+def _shape_error(fn, *a, **kw):
+    import torch  # noqa: F401
+    with pytest.raises(ValueError) as e:
+        fn(*a, **kw)
+    msg = str(e.value)
+    assert "device tensor" not in msg, msg
+    return msg
+
+
+def test_binding_rejects_misshaped_tensors_before_any_launch():
+    import torch
+    w, h = 30, 20
+    rows, cols = fht.hough_shape(w, h)
+    img = torch.zeros((h, w), dtype=torch.float32)
+    G = torch.zeros((rows, cols), dtype=torch.float32)
+    # forward: out of the wrong shape or dtype
+    _shape_error(fht.forward, img, out=torch.zeros((rows - 1, cols)))
+    _shape_error(fht.forward, img, out=torch.zeros((rows, cols), dtype=torch.int32))
+    _shape_error(fht.forward, img, out=torch.zeros((rows, cols)), workspace=torch.zeros(16, dtype=torch.uint8))
+    # adjoint: gradient short by a row, image gradient short by a row
+    _shape_error(fht.adjoint, torch.zeros((rows - 1, cols)), w, h)
+    _shape_error(fht.adjoint, G, w, h, out=torch.zeros((h - 1, w)))
+    _shape_error(fht.adjoint, torch.zeros((fht.hough_shape(w, h, [1])[0], cols)), w, h)  # quadrant, not full
+    # batch adjoint: per-image gradient shape, output shape
+    _shape_error(fht.batch_adjoint, torch.zeros((2, rows, cols - 1)), w, h)
+    _shape_error(fht.batch_adjoint, torch.zeros((2, rows, cols)), w, h, out=torch.zeros((2, h, w - 1)))
+    # fhtshift: a quadrant-only image, or an output of another shape
+    _shape_error(fht.shift, torch.zeros((32, cols)), w, h)
+    _shape_error(fht.shift, G, w, h, out=torch.zeros((rows, cols + 1)))
+    # angle range, scaled range and range adjoint: outputs and gradients
+    S1, S = 3, 9
+    rr, rc = fht.range_shape(w, h, S1, S)
+    _shape_error(fht.range_transform, img, S1, S, out=torch.zeros((rr + 1, rc)))
+    sr, sc = fht.range_scaled_shape(w, h, 2, 1, S1, S)
+    _shape_error(fht.range_scaled, img, 2, 1, S1, S, out=torch.zeros((sr, sc - 1)))
+    _shape_error(fht.range_adjoint, torch.zeros((rr - 1, rc)), w, h, S1, S)
+    _shape_error(fht.range_adjoint, torch.zeros((rr, rc)), w, h, S1, S, out=torch.zeros((h, w + 1)))
+    # rows with a pitch below their width
+    _shape_error(fht.forward, torch.zeros((h, w)).as_strided((h, w), (w - 1, 1)))
+    # correct shapes pass every shape check (a host workspace may then fail
+    # the 256-byte alignment check before the device check)
+    with pytest.raises(ValueError, match="device tensor|256-byte aligned"):
+        fht.forward(img, out=torch.zeros((rows, cols)))
+    with pytest.raises(ValueError, match="device tensor|256-byte aligned"):
+        fht.adjoint(G, w, h, out=torch.zeros((h, w)))
