@@ -29,7 +29,8 @@ def rng_for(name: str, seed: int = 0, index: int = 0) -> np.random.Generator:
 
 
 def _draw_line_steep(img, rng, slope, value, add):
-    """Rasterise x = round(x0 + slope*y) for all rows, x0 so the line crosses."""
+    """Rasterise x = round(x0 + slope*y) for all rows, x0 so the line crosses.
+    Returns the line as (a point on it, its direction): ((x0, 0), (slope, 1))."""
     h, w = img.shape
     lo = min(0.0, -slope * (h - 1))
     hi = max(w - 1.0, w - 1.0 - slope * (h - 1))
@@ -41,6 +42,7 @@ def _draw_line_steep(img, rng, slope, value, add):
         img[ys[ok], xs[ok]] += value
     else:
         img[ys[ok], xs[ok]] = value
+    return dict(point=(float(x0), 0.0), direction=(float(slope), 1.0), pixels=int(ok.sum()))
 
 
 def _draw_line_any(img, rng, value, add):
@@ -61,32 +63,35 @@ def _draw_line_any(img, rng, value, add):
         img[ys[ok], xs[ok]] += value
     else:
         img[ys[ok], xs[ok]] = value
+    return dict(point=(float(px), float(py)), direction=(float(dx), float(dy)), pixels=int(ok.sum()))
 
 
-def binary256(seed: int = 0, size: int = 256) -> np.ndarray:
+# With with_lines=True the workload generators also return the planted lines
+# (a point on each line, its direction and the number of pixels drawn), the
+# ground truth a line detector is checked against.  The random draws are the
+# same either way.
+
+def binary256(seed: int = 0, size: int = 256, with_lines: bool = False):
     rng = rng_for("binary256", seed)
     img = (rng.random((size, size)) < 0.05).astype(np.uint8)
-    for _ in range(3):
-        _draw_line_steep(img, rng, rng.uniform(0.0, 1.0), 1, add=False)
-    return img
+    lines = [_draw_line_steep(img, rng, rng.uniform(0.0, 1.0), 1, add=False) for _ in range(3)]
+    return (img, lines) if with_lines else img
 
 
-def sparse1024(seed: int = 0, size: int = 1024) -> np.ndarray:
+def sparse1024(seed: int = 0, size: int = 1024, with_lines: bool = False):
     rng = rng_for("sparse1024", seed)
     img = np.zeros((size, size), dtype=np.uint8)
     mask = rng.random((size, size)) < 0.02
     img[mask] = rng.integers(0, 256, size=int(mask.sum()), dtype=np.uint8)
-    for _ in range(8):
-        _draw_line_any(img, rng, 255, add=False)
-    return img
+    lines = [_draw_line_any(img, rng, 255, add=False) for _ in range(8)]
+    return (img, lines) if with_lines else img
 
 
-def dense4096(seed: int = 0, size: int = 4096) -> np.ndarray:
+def dense4096(seed: int = 0, size: int = 4096, with_lines: bool = False):
     rng = rng_for("dense4096", seed)
     img = rng.standard_exponential((size, size), dtype=np.float32)
-    for _ in range(16):
-        _draw_line_any(img, rng, np.float32(20.0), add=True)
-    return img
+    lines = [_draw_line_any(img, rng, np.float32(20.0), add=True) for _ in range(16)]
+    return (img, lines) if with_lines else img
 
 
 def batch_sizes(seed: int = 0, count: int = 512, lo: int = 64, hi: int = 2048):

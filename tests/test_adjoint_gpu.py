@@ -5,6 +5,7 @@ import pytest
 import torch
 
 import oracle
+import gpu_util as P
 from gpu_util import assert_close_fp, assert_equal, dev, host
 from paper_1811_06378_amd import fht
 from paper_1811_06378_amd import synth
@@ -26,14 +27,14 @@ def _grad(h, w, kind, seed=0, quads="full"):
 @pytest.mark.parametrize("h,w", SIZES)
 def test_adjoint_int_exact(h, w):
     g = _grad(h, w, "i32")
-    got = host(fht.adjoint(dev(g), w, h))
+    got = host(P.adjoint(dev(g), w, h))
     assert_equal(got.astype(np.float64), oracle.adjoint_full(g.astype(np.float64), w, h), "adjoint i32")
 
 
 @pytest.mark.parametrize("h,w", SIZES)
 def test_adjoint_float(h, w):
     g = _grad(h, w, "f32", seed=1)
-    got = host(fht.adjoint(dev(g), w, h))
+    got = host(P.adjoint(dev(g), w, h))
     assert_equal(got.astype(np.float64), oracle.adjoint_full(g, w, h, single=True), "adjoint f32 vs binary32")
     assert_close_fp(got, oracle.adjoint_full(g, w, h), oracle.adjoint_full(np.abs(g), w, h), "adjoint f32")
 
@@ -42,7 +43,7 @@ def test_adjoint_float(h, w):
 @pytest.mark.parametrize("quads", [[1], [2], [3], [4], [2, 4]])
 def test_adjoint_quadrant_subsets(h, w, quads):
     g = _grad(h, w, "i32", seed=2, quads=quads)
-    got = host(fht.adjoint(dev(g), w, h, quads=quads))
+    got = host(P.adjoint(dev(g), w, h, quads=quads))
     hp, wp = oracle.next_pow2(h), oracle.next_pow2(w)
     want = np.zeros((h, w))
     r = 0
@@ -56,7 +57,7 @@ def test_adjoint_quadrant_subsets(h, w, quads):
 @pytest.mark.parametrize("h,w", [(8, 8), (13, 5), (300, 520)])
 def test_adjoint_shifted(h, w):
     g = _grad(h, w, "i32", seed=3)
-    got = host(fht.adjoint(dev(g), w, h, shifted=True))
+    got = host(P.adjoint(dev(g), w, h, shifted=True))
     unshift = oracle.fhtshift_full(g.astype(np.float64), w, h, inverse=True)
     assert_equal(got.astype(np.float64), oracle.adjoint_full(unshift, w, h), "adjoint shifted")
 
@@ -66,8 +67,8 @@ def test_inner_product_identity_int32(h, w):
     """<F x, y> = <x, F^T y> exactly, both sides from the GPU kernels."""
     x = synth.int_image(h, w, seed=4)
     y = _grad(h, w, "i32", seed=5)
-    Fx = host(fht.forward(dev(x))).astype(np.int64)
-    Fty = host(fht.adjoint(dev(y), w, h)).astype(np.int64)
+    Fx = host(P.forward(dev(x))).astype(np.int64)
+    Fty = host(P.adjoint(dev(y), w, h)).astype(np.int64)
     assert int(np.sum(Fx * y.astype(np.int64))) == int(np.sum(x.astype(np.int64) * Fty))
 
 
@@ -131,7 +132,7 @@ def test_adjoint_ignores_cells_that_reach_no_pixel(h, w, shifted):
     g = rng.standard_normal(ones.shape).astype(np.float32)
     g2 = g.copy()
     g2[mask] = 3.0e38
-    a = host(fht.adjoint(dev(g), w, h, shifted=shifted))
-    b = host(fht.adjoint(dev(g2), w, h, shifted=shifted))
+    a = host(P.adjoint(dev(g), w, h, shifted=shifted))
+    b = host(P.adjoint(dev(g2), w, h, shifted=shifted))
     assert np.array_equal(a, b)
     assert np.all(np.isfinite(b))

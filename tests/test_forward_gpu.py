@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+import gpu_util as P
 from gpu_util import assert_close_fp, assert_equal, dev, host
 from paper_1811_06378_amd import fht
 from paper_1811_06378_amd import synth
@@ -32,7 +33,7 @@ def _oracle_full(img, single=False):
 @pytest.mark.parametrize("kind", ["u8", "i32"])
 def test_full_integer_exact(h, w, kind):
     img = _img(h, w, kind)
-    got = host(fht.forward(dev(img)))
+    got = host(P.forward(dev(img)))
     assert got.dtype == np.int32
     assert_equal(got.astype(np.float64), _oracle_full(img), "full %s %dx%d" % (kind, h, w))
 
@@ -40,7 +41,7 @@ def test_full_integer_exact(h, w, kind):
 @pytest.mark.parametrize("h,w", SIZES)
 def test_full_float(h, w):
     img = _img(h, w, "f32")
-    got = host(fht.forward(dev(img)))
+    got = host(P.forward(dev(img)))
     assert_equal(got.astype(np.float64), _oracle_full(img, single=True), "full f32 vs binary32 oracle")
     assert_close_fp(got, _oracle_full(img), _oracle_full(np.abs(img)), "full f32 vs float64 oracle")
 
@@ -49,7 +50,7 @@ def test_full_float(h, w):
 @pytest.mark.parametrize("quads", [[1], [2], [3], [4], [1, 3], [2, 3, 4]])
 def test_quadrant_subsets(h, w, quads):
     img = _img(h, w, "u8", seed=3)
-    got = host(fht.forward(dev(img), quads=quads))
+    got = host(P.forward(dev(img), quads=quads))
     want = oracle.stacked_quadrants(img, quads)
     assert_equal(got.astype(np.float64), want, "quads %s %dx%d" % (quads, h, w))
 
@@ -58,7 +59,7 @@ def test_quadrant_subsets(h, w, quads):
 @pytest.mark.parametrize("kind", ["u8", "f32"])
 def test_full_shifted(h, w, kind):
     img = _img(h, w, kind, seed=5)
-    got = host(fht.forward(dev(img), shifted=True))
+    got = host(P.forward(dev(img), shifted=True))
     want = oracle.fhtshift_full(_oracle_full(img, single=(kind == "f32")), w, h)
     assert_equal(got.astype(np.float64), want, "shifted %s" % kind)
 
@@ -67,12 +68,11 @@ def test_full_shifted(h, w, kind):
 @pytest.mark.parametrize("inplace", [False, True])
 def test_shift_kernel(h, w, inplace):
     img = _img(h, w, "i32", seed=6)
-    H = fht.forward(dev(img))
+    H = P.forward(dev(img))
     ref = _oracle_full(img)
-    out = H if inplace else None
-    S = fht.shift(H, w, h, out=out)
+    S = fht.shift(H, w, h, out=H) if inplace else P.shift(H, w, h)
     assert_equal(host(S).astype(np.float64), oracle.fhtshift_full(ref, w, h), "fht_shift")
-    back = fht.shift(S, w, h, inverse=True, out=(S if inplace else None))
+    back = fht.shift(S, w, h, inverse=True, out=S) if inplace else P.shift(S, w, h, inverse=True)
     assert_equal(host(back).astype(np.float64), ref, "inverse fht_shift")
 
 
@@ -85,7 +85,7 @@ RANGES = [(8, 8, 0, 7, False), (8, 8, 7, 0, False), (16, 16, 3, 9, False), (16, 
 @pytest.mark.parametrize("kind", ["u8", "f32"])
 def test_range(h, w, S1, S, tr, kind):
     img = _img(h, w, kind, seed=8)
-    got = host(fht.range_transform(dev(img), S1, S, transposed=tr))
+    got = host(P.range_transform(dev(img), S1, S, transposed=tr))
     want = oracle.range_transform(img.astype(np.float64), S1, S, transposed=tr, single=(kind == "f32"))
     assert_equal(got.astype(np.float64), want, "range %dx%d S1=%d S=%d" % (h, w, S1, S))
 
@@ -94,7 +94,7 @@ def test_binary256_quadrant1():
     """256 x 256 binary image, quadrant 1 only, int32: bit-exact vs the oracle
     and vs brute-force pattern sums on sampled cells."""
     img = synth.binary256(0)
-    got = host(fht.forward(dev(img), quads=[1]))
+    got = host(P.forward(dev(img), quads=[1]))
     want = oracle.quadrant(img, 1)
     assert_equal(got.astype(np.float64), want, "binary256 q1")
     rng = np.random.default_rng(1)
@@ -108,20 +108,20 @@ def test_sparse1024_full_shift_range():
     img = synth.sparse1024(0)
     x = dev(img)
     F = _oracle_full(img)
-    assert_equal(host(fht.forward(x)).astype(np.float64), F, "sparse1024 full")
-    assert_equal(host(fht.forward(x, shifted=True)).astype(np.float64), oracle.fhtshift_full(F, 1024, 1024),
+    assert_equal(host(P.forward(x)).astype(np.float64), F, "sparse1024 full")
+    assert_equal(host(P.forward(x, shifted=True)).astype(np.float64), oracle.fhtshift_full(F, 1024, 1024),
                  "sparse1024 shifted")
     S1, S = fht.range_params(1024, -15, 15)
     assert (S1, S) == (275, 550)
-    assert_equal(host(fht.range_transform(x, S1, S)).astype(np.float64),
+    assert_equal(host(P.range_transform(x, S1, S)).astype(np.float64),
                  oracle.range_transform(img, S1, S), "sparse1024 range")
 
 
 def test_repeat_calls_identical():
     img = _img(300, 520, "f32", seed=9)
     x = dev(img)
-    a = host(fht.forward(x))
-    b = host(fht.forward(x))
+    a = host(P.forward(x))
+    b = host(P.forward(x))
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
@@ -133,7 +133,8 @@ def test_pitched_buffers():
     x = dev(big)[:, :90]
     rows, cols = fht.hough_shape(90, 77)
     out_big = torch.full((rows, cols + 37), -7, dtype=torch.int32, device="cuda")
-    fht.forward(x, out=out_big[:, :cols])
+    out_big[:, :cols].fill_(P.SENTINEL_I32)
+    fht.forward(x, out=out_big[:, :cols], workspace=P.poisoned_ws(fht.workspace_size(90, 77, "full", torch.int32)))
     got = host(out_big)
     assert_equal(got[:, :cols].astype(np.float64), _oracle_full(img), "pitched")
     assert np.all(got[:, cols:] == -7)
@@ -154,6 +155,6 @@ def test_byte_image_any_alignment(col0, pitch):
     x = dev(big)[:, col0:col0 + w]
     assert x.stride(0) == pitch
     want = _oracle_full(img)
-    assert_equal(host(fht.forward(x)).astype(np.float64), want, "u8 col0=%d pitch=%d" % (col0, pitch))
-    got_s = host(fht.forward(x, shifted=True)).astype(np.float64)
+    assert_equal(host(P.forward(x)).astype(np.float64), want, "u8 col0=%d pitch=%d" % (col0, pitch))
+    got_s = host(P.forward(x, shifted=True)).astype(np.float64)
     assert_equal(got_s, oracle.fhtshift_full(want, w, h), "u8 shifted col0=%d pitch=%d" % (col0, pitch))

@@ -2,23 +2,28 @@
 configuration, on outputs the oracle can compute one by one and on
 properties that hold at any size.
 
-dense4096 (4096^2 float32, full transform): sampled cells against the
-oracle's direct pattern sums; every row sums to the image total; the
-junction rows of the four quadrants agree (bitwise where both quadrants sum
-in the same order).
+dense4096 (4096^2 float32, full transform, poisoned output and workspace):
+every cell bit for bit against the oracle's binary32 recurrence and within
+1e-5 * FHT(|I|) of the float64 oracle; sampled cells against the oracle's
+direct pattern sums; every row sums to the image total; the junction rows of
+the four quadrants agree (bitwise where both quadrants sum in the same
+order).
 
-normal1024 (16 x 1024^2 float32, differentiable): the autograd gradient of
-sum(W * H^2) against the float64 transpose and against float64 central
-differences (relative 1e-4); the exact inner-product identity on int32
-images; 200 gradient-descent steps fitting an image to a target Hough image
-with a non-increasing loss, the first iterates tracking the float64 oracle.
+normal1024 (16 x 1024^2 float32, differentiable): every image's forward and
+gradient bit for bit against the oracle's binary32 recurrence and transpose;
+the autograd gradient of sum(W * H^2) against the float64 transpose and
+against float64 central differences (relative 1e-4) for all 16 images; the
+exact inner-product identity on int32 images; 200 gradient-descent steps
+fitting an image to a target Hough image with a non-increasing loss, the
+first iterates tracking the float64 oracle.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from gpu_util import dev, host
+import gpu_util as P
+from gpu_util import assert_close_fp, assert_equal, dev, host
 from paper_1811_06378_amd import fht, synth
 
 pytestmark = pytest.mark.gpu
@@ -26,14 +31,27 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def dense4096():
+    """The benchmark's configuration: one full transform of the 4096^2 float32
+    image into a poisoned output with a poisoned workspace."""
     img = synth.dense4096(0)
-    x = dev(img)
-    rows, cols = fht.hough_shape(4096, 4096)
-    out = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
-    ws = torch.empty(max(fht.workspace_size(4096, 4096, "full", torch.float32), 256), dtype=torch.uint8,
-                     device="cuda")
-    fht.forward(x, out=out, workspace=ws)
-    return img, host(out)
+    H = host(P.forward(dev(img)))
+    return img, H
+
+
+def test_dense4096_whole_image_bit_exact_against_binary32_oracle(dense4096):
+    """Every one of the 16381 x 8192 cells equals the oracle's binary32 stage
+    recurrence (the same add tree) bit for bit."""
+    img, H = dense4096
+    want = oracle.full(img, single=True)
+    assert_equal(H.astype(np.float64), want, "dense4096 vs binary32 oracle")
+
+
+def test_dense4096_whole_image_within_1e5_of_float64_oracle(dense4096):
+    """Every cell within 1e-5 * FHT(|I|) of the float64 oracle (the image is
+    non-negative, so FHT(|I|) is the float64 result itself)."""
+    img, H = dense4096
+    want = oracle.full(img)
+    assert_close_fp(H, want, want, "dense4096 vs float64 oracle")
 
 
 def test_dense4096_sampled_cells(dense4096):
@@ -62,8 +80,8 @@ def test_dense4096_junction_rows_agree():
     img = synth.dense4096(0)
     x = dev(img)
     # two stacked pairs (all four bits would select the merged full image)
-    A = host(fht.forward(x, quads=[1, 2]))
-    B = host(fht.forward(x, quads=[3, 4]))
+    A = host(P.forward(x, quads=[1, 2]))
+    B = host(P.forward(x, quads=[3, 4]))
     q1, q2, q3, q4 = A[:4096], A[4096:], B[:4096], B[4096:]
     assert np.array_equal(q1[0], q2[0])          # column sums, same add order
     assert np.array_equal(q3[0], q4[0])          # row sums, same add order
@@ -80,13 +98,32 @@ def normal1024():
     Wt = synth.weight_map((rows, cols), 0)
     x = dev(X).requires_grad_(True)
     H = fht.fht(x)
+    upstream = []
+    H.register_hook(lambda g: upstream.append(g.detach().clone()))
     (dev(Wt) * H * H).sum().backward()
-    return X, Wt, host(x.grad)
+    return X, Wt, host(x.grad), host(H.detach()), host(upstream[0])
 
 
-@pytest.mark.parametrize("i", [0, 9, 15])
+@pytest.mark.parametrize("i", range(16))
+def test_normal1024_forward_bit_exact(normal1024, i):
+    """The stacked forward of the autograd path (one batch plan) equals the
+    oracle's binary32 recurrence on every cell of every image."""
+    X, _, _, H, _ = normal1024
+    assert_equal(H[i].astype(np.float64), oracle.full(X[i], single=True), "normal1024 forward %d" % i)
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_normal1024_backward_bit_exact(normal1024, i):
+    """The stacked backward (side streams, up to four images per launch)
+    equals the oracle's binary32 transpose of the same upstream gradient."""
+    _, _, G, _, U = normal1024
+    assert_equal(G[i].astype(np.float64), oracle.adjoint_full(U[i], 1024, 1024, single=True),
+                 "normal1024 gradient %d" % i)
+
+
+@pytest.mark.parametrize("i", range(16))
 def test_normal1024_gradient_matches_float64_transpose(normal1024, i):
-    X, Wt, G = normal1024
+    X, Wt, G, _, _ = normal1024
     x = X[i].astype(np.float64)
     WF = Wt.astype(np.float64) * oracle.full(x)
     want = 2.0 * oracle.adjoint_full(WF, 1024, 1024)
@@ -94,11 +131,11 @@ def test_normal1024_gradient_matches_float64_transpose(normal1024, i):
     assert np.all(np.abs(G[i] - want) <= 1e-4 * scale + 1e-6)
 
 
-@pytest.mark.parametrize("i", [0, 15])
+@pytest.mark.parametrize("i", range(16))
 def test_normal1024_gradient_matches_central_differences(normal1024, i):
     """<grad, v> against (L(x + e v) - L(x - e v)) / 2e computed in float64
     by the oracle (exact up to rounding for this quadratic loss)."""
-    X, Wt, G = normal1024
+    X, Wt, G, _, _ = normal1024
     x = X[i].astype(np.float64)
     v = np.random.default_rng(100 + i).standard_normal((1024, 1024))
     W64 = Wt.astype(np.float64)
@@ -117,9 +154,9 @@ def test_normal1024_gradient_matches_central_differences(normal1024, i):
 def test_normal1024_inner_product_identity_int32():
     rng = np.random.default_rng(4)
     x = rng.integers(-1000, 1001, size=(1024, 1024)).astype(np.int32)
-    Fx = host(fht.forward(dev(x))).astype(np.int64)
+    Fx = host(P.forward(dev(x))).astype(np.int64)
     y = rng.integers(-1000, 1001, size=Fx.shape).astype(np.int32)
-    Fty = host(fht.adjoint(dev(y), 1024, 1024)).astype(np.int64)
+    Fty = host(P.adjoint(dev(y), 1024, 1024)).astype(np.int64)
     assert int(np.sum(Fx * y)) == int(np.sum(x.astype(np.int64) * Fty))
 
 
@@ -129,21 +166,21 @@ def test_normal1024_gradient_descent_fit():
     iteration: the loss never increases; the first iterates match the same
     iteration run on the float64 oracle."""
     T = synth.normal1024(1, batch=1)[0]
-    Y = fht.forward(dev(T))
+    Y = P.forward(dev(T))
     # power iteration for the largest eigenvalue of F^T F
     v = torch.ones((1024, 1024), dtype=torch.float32, device="cuda")
     lam = 0.0
     for _ in range(30):
-        u = fht.adjoint(fht.forward(v), 1024, 1024)
+        u = P.adjoint(P.forward(v), 1024, 1024)
         lam = float(torch.linalg.vector_norm(u) / torch.linalg.vector_norm(v))
         v = u / torch.linalg.vector_norm(u)
     eta = 1.0 / (2.0 * 1.1 * lam)
     x = torch.zeros((1024, 1024), dtype=torch.float32, device="cuda")
     losses, iterates = [], []
     for k in range(200):
-        R = fht.forward(x) - Y
+        R = P.forward(x) - Y
         losses.append(float(torch.sum(R.double() ** 2)))
-        x = x - eta * 2.0 * fht.adjoint(R, 1024, 1024)
+        x = x - eta * 2.0 * P.adjoint(R, 1024, 1024)
         if k < 3:
             iterates.append(host(x).astype(np.float64))
     # the same iteration in float64 on the oracle

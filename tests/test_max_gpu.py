@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+import gpu_util as P
 from gpu_util import assert_equal, dev, host
 from paper_1811_06378_amd import fht, synth
 
@@ -20,7 +21,7 @@ SIZES = [(1, 1), (2, 3), (4, 4), (5, 13), (8, 8), (16, 16), (9, 40), (64, 64), (
 @pytest.mark.parametrize("kind", ["u8", "i32", "f32"])
 def test_max_full_exact(h, w, kind):
     img = synth.random_image(h, w, kind, seed=21)
-    got = host(fht.forward(dev(img), op="max"))
+    got = host(P.forward(dev(img), op="max"))
     want = oracle.full_op(img.astype(np.float64), "max")
     assert_equal(got.astype(np.float64), want, "max full %s %dx%d" % (kind, h, w))
 
@@ -29,7 +30,7 @@ def test_max_full_exact(h, w, kind):
 @pytest.mark.parametrize("quads", [[1], [2], [3], [4], [2, 3]])
 def test_max_quadrant_subsets(h, w, quads):
     img = synth.random_image(h, w, "i32", seed=4)
-    got = host(fht.forward(dev(img), quads=quads, op="max"))
+    got = host(P.forward(dev(img), quads=quads, op="max"))
     want = np.concatenate([oracle.quadrant_op(img.astype(np.float64), q, "max") for q in sorted(quads)], axis=0)
     assert_equal(got.astype(np.float64), want, "max quads %s %dx%d" % (quads, h, w))
 
@@ -37,7 +38,7 @@ def test_max_quadrant_subsets(h, w, quads):
 @pytest.mark.parametrize("h,w", [(8, 8), (13, 5), (300, 520)])
 def test_max_shifted(h, w):
     img = synth.random_image(h, w, "u8", seed=6)
-    got = host(fht.forward(dev(img), shifted=True, op="max"))
+    got = host(P.forward(dev(img), shifted=True, op="max"))
     want = oracle.fhtshift_full(oracle.full_op(img.astype(np.float64), "max"), w, h)
     assert_equal(got.astype(np.float64), want, "max shifted %dx%d" % (h, w))
 
@@ -46,12 +47,12 @@ def test_max_binary_is_or_of_sum():
     """On the 256^2 binary workload max equals (sum > 0), both from the GPU."""
     img = synth.binary256(0)
     x = dev(img)
-    s = fht.forward(x)
-    m = fht.forward(x, op="max")
+    s = P.forward(x)
+    m = P.forward(x, op="max")
     assert torch.equal(m, (s > 0).to(torch.int32))
 
 
 def test_max_sparse1024_full():
     img = synth.sparse1024(0)
-    got = host(fht.forward(dev(img), op="max"))
+    got = host(P.forward(dev(img), op="max"))
     assert_equal(got.astype(np.float64), oracle.full_op(img.astype(np.float64), "max"), "max sparse1024")

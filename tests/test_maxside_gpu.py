@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import oracle
+import gpu_util as P
 from gpu_util import dev
 from paper_1811_06378_amd import fht, synth
 
@@ -18,7 +19,7 @@ pytestmark = pytest.mark.gpu
 def test_max_side_forward_and_shift(h, w):
     img = synth.random_image(h, w, "u8", seed=65)
     x = dev(img)
-    H = fht.forward(x)
+    H = P.forward(x)
     rows, cols = H.shape
     assert (rows, cols) == fht.hough_shape(w, h) == (131085, 65544)
     rng = np.random.default_rng(1)

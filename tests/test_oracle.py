@@ -322,6 +322,51 @@ def test_range_peak_follows_planted_slope(oracle_mod):
         assert abs((s_peak - S1) - t * (n - 1)) <= 3
 
 
+@pytest.mark.parametrize("h,w", [(32, 32), (16, 40), (64, 24)])
+def test_range_sheared_black_zone_moves_without_cyclic_effect(oracle_mod, h, w):
+    """Section 4, Fig. 5: after a horizontal shear by arctg(1/2) the zero
+    extension keeps the sheared image from wrapping around, and the black
+    zone only moves and changes its shape.
+
+    Built independently of the oracle's recurrence: with
+    f_s(y) = D(s, y) - sigma(y) (pattern offset minus the row's shear, both
+    moving by 0 or 1 column per row, so f_s takes every value between its
+    extremes), the pattern of row s at x0 meets the image iff
+    x0 + f_s(y) is in [0, w) for some image row y.  On an all-white image
+    the zero cells of row s are therefore exactly one cyclic run of
+    W - w - (max f_s - min f_s) columns starting at w - min f_s.  And on a white cross the
+    cyclic shear equals the explicit shear of the image onto a wider canvas
+    (no pixel wraps round)."""
+    hp, wp = bf.pow2_ceil(h), bf.pow2_ceil(w)
+    W = hp + wp
+    n = hp
+    S1 = (n - 1) // 2                      # shear of about arctg(1/2): sigma(y) ~ y / 2
+    sigma = [math.floor((2 * y * S1 + (n - 1)) / (2 * (n - 1))) for y in range(n)]
+    # all-white image: the zero cells of every row form the predicted run
+    R = oracle_mod.range_transform(np.ones((h, w)), S1, n - 1)
+    for s in range(n):
+        f = [bf.pattern_closed_form(n, s, y) - sigma[y] for y in range(h)]
+        lo, hi = min(f), max(f)
+        zero = np.zeros(W, dtype=bool)
+        assert W - w - (hi - lo) > 0        # the run never closes: no cyclic effect
+        for k in range(W - w - (hi - lo)):
+            zero[(w - lo + k) % W] = True
+        assert np.array_equal(R[s] == 0, zero), s
+        assert np.all(R[s][~zero] > 0)
+    # a white cross: the cyclic shear equals the explicit one on a canvas wide
+    # enough that nothing can wrap, summed along the patterns by brute force
+    cross = np.zeros((h, w))
+    cross[h // 2 - 1:h // 2 + 1, :] = 1.0
+    cross[:, w // 2 - 1:w // 2 + 1] = 1.0
+    canvas = np.zeros((n, W))
+    for y in range(h):
+        canvas[y, sigma[y]:sigma[y] + w] = cross[y]       # sigma(y) + w <= W: no wrap
+    assert max(sigma) + w <= W
+    tab = bf.pattern_table(n)
+    want = np.array([[canvas[np.arange(n), (x + tab[s]) % W].sum() for x in range(W)] for s in range(n)])
+    np.testing.assert_array_equal(oracle_mod.range_transform(cross, S1, n - 1), want)
+
+
 # -------------------------------------------------------------------- adjoint
 
 @pytest.mark.parametrize("h,w", [(1, 1), (3, 5), (8, 8), (16, 7), (5, 33)])

@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+import gpu_util as P
 from gpu_util import assert_close_fp, assert_equal, dev, host
 from paper_1811_06378_amd import fht, synth
 
@@ -33,7 +34,7 @@ def _grad(shape, kind, seed):
 def test_range_adjoint_int_exact(h, w, S1, S, tr):
     rows, cols = fht.range_shape(w, h, S1, S, tr)
     g = _grad((rows, cols), "i32", seed=h + w + S)
-    got = host(fht.range_adjoint(dev(g), w, h, S1, S, tr))
+    got = host(P.range_adjoint(dev(g), w, h, S1, S, tr))
     want = oracle.range_adjoint(g.astype(np.float64), w, h, S1, S, tr)
     assert_equal(got.astype(np.float64), want, "range adjoint %dx%d S1=%d S=%d tr=%d" % (h, w, S1, S, tr))
 
@@ -42,7 +43,7 @@ def test_range_adjoint_int_exact(h, w, S1, S, tr):
 def test_range_adjoint_float(h, w, S1, S, tr):
     rows, cols = fht.range_shape(w, h, S1, S, tr)
     g = _grad((rows, cols), "f32", seed=7 * h + w)
-    got = host(fht.range_adjoint(dev(g), w, h, S1, S, tr))
+    got = host(P.range_adjoint(dev(g), w, h, S1, S, tr))
     g64 = g.astype(np.float64)
     assert_equal(got.astype(np.float64), oracle.range_adjoint(g64, w, h, S1, S, tr, single=True),
                  "range adjoint f32 vs binary32 oracle")
@@ -56,9 +57,9 @@ def test_range_inner_product_identity_on_gpu(h, w, S1, S, tr):
     """<R x, g> = <x, R^T g> with both sides from the GPU, in int64."""
     rng = np.random.default_rng(3)
     x = rng.integers(-100, 101, size=(h, w)).astype(np.int32)
-    Rx = host(fht.range_transform(dev(x), S1, S, tr)).astype(np.int64)
+    Rx = host(P.range_transform(dev(x), S1, S, tr)).astype(np.int64)
     g = rng.integers(-100, 101, size=Rx.shape).astype(np.int32)
-    Rtg = host(fht.range_adjoint(dev(g), w, h, S1, S, tr)).astype(np.int64)
+    Rtg = host(P.range_adjoint(dev(g), w, h, S1, S, tr)).astype(np.int64)
     assert int(np.sum(Rx * g)) == int(np.sum(x.astype(np.int64) * Rtg))
 
 
@@ -100,6 +101,6 @@ SCALED = [(64, 64, 2, 1, 0, 63, False), (64, 64, 1, 2, 5, 40, False), (100, 70, 
 @pytest.mark.parametrize("kind", ["u8", "f32"])
 def test_range_scaled(h, w, num, den, S1, S, tr, kind):
     img = synth.random_image(h, w, kind, seed=30 + num)
-    got = host(fht.range_scaled(dev(img), num, den, S1, S, tr))
+    got = host(P.range_scaled(dev(img), num, den, S1, S, tr))
     want = oracle.range_scaled(img.astype(np.float64), num, den, S1, S, tr, single=(kind == "f32"))
     assert_equal(got.astype(np.float64), want, "range scaled %dx%d %d/%d S1=%d S=%d tr=%d" % (h, w, num, den, S1, S, tr))
