@@ -231,9 +231,11 @@ int fht_range_adjoint(const void* grad, int t, int64_t ld_grad, int S1, int S, i
  * whose intermediate bands fit 8 GiB, which bounds the workspace.
  *
  * fht_batch_plan_create: ws[i], hs[i] are the n image sizes (host arrays),
- *   every side >= 5 (FHT_ERR_UNSUPPORTED otherwise; transform such tiny
- *   images with fht_forward).  Allocates the plan's device tables (the only
- *   allocating entry point) on the current device.  *ws_bytes receives the
+ *   any sides from 1 to FHT_MAX_SIDE; quadrants of at most 4 rows run as
+ *   one thread per Hough cell inside the same plan.  FHT_ERR_UNSUPPORTED if
+ *   one launch class of one chunk would exceed 2^31 work items.  Allocates
+ *   the plan's device tables (the only allocating entry point) on the
+ *   current device.  *ws_bytes receives the
  *   workspace size, *out_elems the total number of output elements;
  *   out_offsets (host, n entries, may be NULL) receives each image's element
  *   offset in the packed output (each image's Hough image is stored densely,

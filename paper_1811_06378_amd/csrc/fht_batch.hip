@@ -88,8 +88,6 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
     for (int i = 0; i < n; ++i) {
         int rc = check_sides(ws[i], hs[i]);
         if (rc) return rc;
-        if (ws[i] < 5 || hs[i] < 5)
-            return fail(FHT_ERR_UNSUPPORTED, "batched images need sides >= 5 (image %d is %dx%d)", i, hs[i], ws[i]);
     }
     fht_batch_plan* P = new fht_batch_plan();
     P->n = n;
@@ -152,7 +150,9 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
                     // pointer slots are filled per call; offsets go to the side record
                     it.e.d = make_pass_desc(g, p, nullptr, ws[i], hs[i], ws[i], nullptr, c, nullptr, 0, INT_MAX,
                                             base, sign, skip, 0, ra, rb);
-                    it.e.count = it.e.d.n_row_tiles * it.e.d.n_windows;
+                    // quadrants of at most 4 rows (k <= 2) run as direct cells: n x W
+                    // items each; the others as tiles
+                    it.e.count = g.k <= 2 ? g.n * g.W : it.e.d.n_row_tiles * it.e.d.n_windows;
                     it.e.dep = -1;
                     it.r.img = i;
                     it.r.src_is_ws = p > 0;
@@ -167,22 +167,26 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
             }
         }
         for (int p = 0; p < 4; ++p)
-            for (int G = kMaxG; G >= 3; --G)
+            for (int G = kMaxG; G >= 0; --G)
                 for (int last = 0; last < 2; ++last) {
                     BatchLaunch L{};
                     L.first_group = (int)tmpl.size();
-                    int item = 0;
+                    int64_t item = 0;
                     for (const Item& it : items) {
                         if (it.p != p || it.G != G || it.last != last) continue;
                         EngineGroup e = it.e;
-                        e.first_item = item;
+                        e.first_item = (int)item;
                         item += e.count;
+                        if (item > INT_MAX) {
+                            delete P;
+                            return fail(FHT_ERR_UNSUPPORTED, "more than 2^31 work items of one kind in one chunk");
+                        }
                         tmpl.push_back(e);
                         rel.push_back(it.r);
                     }
                     L.n_groups = (int)tmpl.size() - L.first_group;
                     if (L.n_groups == 0) continue;
-                    L.n_items = item;
+                    L.n_items = (int)item;
                     L.G = G;
                     L.first = p == 0;
                     L.last = last != 0;
@@ -235,8 +239,11 @@ int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* ho
     if (e != hipSuccess) return hip_fail(e, "batch fixup launch");
     const int ti = P->in_t;
     for (const BatchLaunch& L : P->launches) {
-        e = launch_table(table + L.first_group, L.n_groups, L.n_items, L.G, L.first, L.last, L.first ? ti : P->acc_t,
-                         P->acc_t, s);
+        if (L.G <= 2)  // quadrants of at most 4 rows: one thread per Hough cell
+            e = launch_table_direct(table + L.first_group, L.n_groups, L.n_items, ti, P->acc_t, s);
+        else
+            e = launch_table(table + L.first_group, L.n_groups, L.n_items, L.G, L.first, L.last,
+                             L.first ? ti : P->acc_t, P->acc_t, s);
         if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }
     return FHT_OK;

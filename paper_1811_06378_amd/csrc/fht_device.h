@@ -1120,6 +1120,35 @@ __global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
     dst[mod_pos((long long)x + roll, d.W)] = v;
 }
 
+// Direct quadrants (n <= 4 rows) of many images in one launch: one thread
+// per Hough cell, cells of consecutive groups back to back (first_item
+// prefix, n x W cells per group).
+template <typename TIn, typename T>
+__global__ __launch_bounds__(256) void fht_table_direct_kernel(const EngineGroup* __restrict__ table, int n_groups,
+                                                                int n_items)
+{
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= n_items) return;
+    int lo = 0, hi = n_groups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].first_item <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const PassDesc& d = table[lo].d;
+    const int local = item - table[lo].first_item;
+    const int s = local / d.W;
+    const int x = local - s * d.W;
+    if (s >= d.n || s > d.row_limit || s == d.skip_row) return;
+    T v;
+    if (d.n == 1) v = direct_sum<TIn, T, 0, 0>(d, 0, s, x);
+    else if (d.n == 2) v = direct_sum<TIn, T, 1, 0>(d, 0, s, x);
+    else v = direct_sum<TIn, T, 2, 0>(d, 0, s, x);
+    T* dst = reinterpret_cast<T*>(d.dst) + (long long)(d.row_base + d.row_sign * s) * d.dst_ld;
+    const int roll = d.shifted ? ((d.roll_a + d.roll_b * s) >> 1) : 0;
+    dst[mod_pos((long long)x + roll, d.W)] = v;
+}
+
 // Adjoint for n <= 4 rows: B_j from B_{j+1} by the transposed stage, top-down
 // in x.
 template <typename T, int J, int K>

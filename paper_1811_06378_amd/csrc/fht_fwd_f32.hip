@@ -13,4 +13,8 @@ hipError_t launch_table_f32(const EngineGroup* table, int n_groups, int n_items,
 {
     return launch_table_t<float, float>(table, n_groups, n_items, G, first, last, s);
 }
+hipError_t launch_table_direct_f32(const EngineGroup* table, int n_groups, int n_items, hipStream_t s)
+{
+    return launch_table_direct_t<float, float>(table, n_groups, n_items, s);
+}
 }  // namespace fht

@@ -13,4 +13,8 @@ hipError_t launch_table_i32(const EngineGroup* table, int n_groups, int n_items,
 {
     return launch_table_t<int, int>(table, n_groups, n_items, G, first, last, s);
 }
+hipError_t launch_table_direct_i32(const EngineGroup* table, int n_groups, int n_items, hipStream_t s)
+{
+    return launch_table_direct_t<int, int>(table, n_groups, n_items, s);
+}
 }  // namespace fht

@@ -126,6 +126,9 @@ hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc
 // table: device array of n_groups groups of one kind (same G, first/last)
 hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int in_t,
                         int acc_t, hipStream_t s);
+// direct quadrants (n <= 4) of a batch: n x W cells per group
+hipError_t launch_table_direct(const EngineGroup* table, int n_groups, int n_items, int in_t, int acc_t,
+                               hipStream_t s);
 hipError_t launch_adjoint_pass(const AdjLaunch& L, int t, hipStream_t s);
 hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s);

@@ -85,6 +85,15 @@ hipError_t launch_engine_t(const EngineArgs& A, int G, int grid, hipStream_t s)
     }
 }
 
+template <typename TIn, typename T>
+hipError_t launch_table_direct_t(const EngineGroup* table, int n_groups, int n_items, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fht_table_direct_kernel<TIn, T>), dim3((n_items + 255) / 256), dim3(256), 0, s, table,
+                       n_groups, n_items);
+    return hipGetLastError();
+}
+
 template <typename TIn, typename T, int OP = 0>
 hipError_t launch_direct_t(const PassLaunch& L, int k, hipStream_t s)
 {
@@ -160,7 +169,8 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
     hipError_t launch_engine_##name(const EngineArgs& A, int G, int grid, hipStream_t s); \
     hipError_t launch_direct_##name(const PassLaunch& L, int k, hipStream_t s);                 \
     hipError_t launch_table_##name(const EngineGroup* table, int n_groups, int n_items, int G, bool first, \
-                                   bool last, hipStream_t s);
+                                   bool last, hipStream_t s);                                            \
+    hipError_t launch_table_direct_##name(const EngineGroup* table, int n_groups, int n_items, hipStream_t s);
 FHT_DECLARE_FWD(u8)
 FHT_DECLARE_FWD(i32)
 FHT_DECLARE_FWD(f32)

@@ -70,6 +70,15 @@ hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int
     return e;
 }
 
+hipError_t launch_table_direct(const EngineGroup* table, int n_groups, int n_items, int in_t, int acc_t,
+                               hipStream_t s)
+{
+    if (in_t == 0 && acc_t == 1) return launch_table_direct_u8(table, n_groups, n_items, s);
+    if (in_t == 1 && acc_t == 1) return launch_table_direct_i32(table, n_groups, n_items, s);
+    if (in_t == 2 && acc_t == 2) return launch_table_direct_f32(table, n_groups, n_items, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s, int op)
 {
     if (op == 1) {

@@ -512,7 +512,7 @@ BACKWARD_STREAMS = 2
 
 def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False) -> torch.Tensor:
     """Hough images of a (batch, h, w) stack of same-size images, into one
-    (batch, rows, cols) tensor.  Without fhtshift and with sides >= 5 this is
+    (batch, rows, cols) tensor.  Without fhtshift this is
     one batch plan (one launch per pass class for the whole stack, cached per
     shape); otherwise one forward per image, each written in place."""
     if x.dim() != 3:
@@ -525,7 +525,7 @@ def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False) -> torch
     out = torch.empty((n, rows, cols), dtype=odt, device=x.device)
     if n == 0:
         return out
-    if shifted or h < 5 or w < 5 or n == 1:
+    if shifted or n == 1:
         for i in range(n):
             forward(x[i], q, shifted, out=out[i])
         return out

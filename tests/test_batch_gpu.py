@@ -36,6 +36,25 @@ def test_small_batch_matches_oracle(kind):
         assert_equal(got.astype(np.float64), want, "batch %s %dx%d" % (kind, h, w))
 
 
+TINY = [(1, 1), (1, 7), (7, 1), (2, 3), (3, 2), (4, 4), (2, 100), (100, 3), (4, 37), (5, 5), (64, 64), (1, 300)]
+
+
+@pytest.mark.parametrize("kind", ["u8", "i32", "f32"])
+def test_batch_with_tiny_sides_matches_oracle(kind):
+    """Sides 1..4 (quadrants of at most 4 rows run as direct cells inside the
+    plan) mixed with ordinary images: every image bit-exact."""
+    imgs = [synth.random_image(h, w, kind, seed=30 + i) for i, (h, w) in enumerate(TINY)]
+    dt = {"u8": torch.uint8, "i32": torch.int32, "f32": torch.float32}[kind]
+    plan = fht.BatchPlan(TINY, in_dtype=dt)
+    for (h, w), x, got in zip(TINY, imgs, _run(plan, imgs)):
+        want = oracle.full(x.astype(np.float64), single=(kind == "f32"))
+        assert_equal(got.astype(np.float64), want, "tiny batch %s %dx%d" % (kind, h, w))
+    plan_q = fht.BatchPlan(TINY, quads=[2, 4], in_dtype=dt)
+    for x, got in zip(imgs, _run(plan_q, imgs)):
+        assert_equal(got.astype(np.float64), oracle.stacked_quadrants(x.astype(np.float64), [2, 4],
+                                                                       single=(kind == "f32")), "tiny batch q2,q4")
+
+
 @pytest.mark.parametrize("quads", [[1], [2, 3], [4]])
 def test_batch_quadrant_subsets(quads):
     sizes = SMALL[:8]
