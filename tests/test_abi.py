@@ -167,11 +167,17 @@ def test_batch_plan_host_side():
     L = fht.lib()
     p = ctypes.c_void_p()
     wsb, tot = ctypes.c_size_t(), ctypes.c_int64()
-    ws = (ctypes.c_int32 * 2)(3, 8)
+    ws = (ctypes.c_int32 * 2)(0, 8)
     hs = (ctypes.c_int32 * 2)(8, 8)
     assert L.fht_batch_plan_create(ws, hs, 2, 15, 0, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
-                                   None) == fht.FHT_ERR_UNSUPPORTED
+                                   None) == fht.FHT_ERR_INVALID
+    ws[0] = 65537
+    assert L.fht_batch_plan_create(ws, hs, 2, 15, 0, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
+                                   None) == fht.FHT_ERR_INVALID
+    ws[0] = 3
     assert L.fht_batch_plan_create(ws, hs, 2, 15, 2, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
+                                   None) == fht.FHT_ERR_INVALID
+    assert L.fht_batch_plan_create(ws, hs, 2, 0, 0, 1, ctypes.byref(p), ctypes.byref(wsb), ctypes.byref(tot),
                                    None) == fht.FHT_ERR_INVALID
     assert L.fht_batch_plan_destroy(None) == 0
 
