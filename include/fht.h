@@ -127,6 +127,27 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
                 size_t ws_bytes, void* stream);
 
 /*
+ * Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as fht_forward, without
+ * the workspace: the scratch (intermediate bands) is a file-scope device
+ * array of FHT_NOALLOC_SCRATCH_BYTES that the library's code object holds on
+ * every GPU it runs on until the process ends; its address is looked up once
+ * per device, on that device's first call.  The call allocates nothing,
+ * frees nothing and calls no allocating routine.
+ *   Limit: transforms whose fht_workspace_size exceeds
+ *   FHT_NOALLOC_SCRATCH_BYTES return FHT_ERR_UNSUPPORTED (the full image of
+ *   a 2048 x 1024 image fits, for every dtype; 2048 x 2048 does not).
+ *   Sharing: every call on one GPU uses that GPU's one array, whose contents
+ *   are left from the last call (no call relies on them).  Calls that overlap
+ *   in time on one GPU (two streams, two threads, or a graph replay beside an
+ *   eager call) race on it: order them on one stream or use fht_forward.
+ */
+#define FHT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fht_forward_noalloc(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t,
+                        int64_t ld_hough, unsigned quads, unsigned flags, void* stream);
+
+/*
  * Angle-range transform (section 4).  Shifts s = 0..S of quadrant 1 (quadrant
  * 4 of the transposed image when transposed != 0) computed on the image whose
  * row y is read cyclically pre-shifted right by

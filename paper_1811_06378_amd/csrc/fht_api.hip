@@ -640,8 +640,12 @@ int fht_range_workspace_size(int w, int h, int S1, int S, int transposed, int in
     return FHT_OK;
 }
 
-int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t, int64_t ld_hough,
-                unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace fht {
+
+int forward_check(const void* img, int in_t, int w, int h, int64_t ld_img, const void* hough, int acc_t,
+                  int64_t ld_hough, unsigned quads, unsigned flags, size_t* need)
 {
     int64_t rows, cols;
     int rc = fht_hough_shape(w, h, quads, &rows, &cols);
@@ -657,7 +661,25 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    const size_t need = forward_workspace(gs, nq, acc_t);
+    *need = forward_workspace(gs, nq, acc_t);
+    return FHT_OK;
+}
+
+}  // namespace fht
+
+extern "C" {
+
+int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* hough, int acc_t, int64_t ld_hough,
+                unsigned quads, unsigned flags, void* workspace, size_t ws_bytes, void* stream)
+{
+    size_t need = 0;
+    int rc = forward_check(img, in_t, w, h, ld_img, hough, acc_t, ld_hough, quads, flags, &need);
+    if (rc) return rc;
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    forward_workspace(gs, nq, acc_t);  // lays out the bands in gs
     if (!workspace || ws_bytes < need)
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");

@@ -39,6 +39,10 @@ QuadGeom quad_geom(int w, int h, int q, int S1);
 size_t quad_band_bytes(const QuadGeom& g, int p, int elem);
 size_t layout_bands(QuadGeom* gs, int nq, int elem, size_t base);
 int check_sides(int w, int h);
+// Validates fht_forward's arguments (host only, no HIP call) and returns the
+// workspace bytes the call needs in *need.
+int forward_check(const void* img, int in_t, int w, int h, int64_t ld_img, const void* hough, int acc_t,
+                  int64_t ld_hough, unsigned quads, unsigned flags, size_t* need);
 int selected_quads(unsigned quads, int* qs);
 void placement(int w, int h, unsigned quads, int q, int* base, int* sign, int* skip, int* roll_a, int* roll_b);
 PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int w, int h, int64_t ld_img, void* hough,

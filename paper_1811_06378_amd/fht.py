@@ -59,6 +59,7 @@ SIGNATURES = {
     "fht_range_workspace_size": (_I, [_I, _I, _I, _I, _I, _I, _I, _PSZ]),
     "fht_adjoint_workspace_size": (_I, [_I, _I, _U, _I, _PSZ]),
     "fht_forward": (_I, [_P, _I, _I, _I, _I64, _P, _I, _I64, _U, _U, _P, _SZ, _P]),
+    "fht_forward_noalloc": (_I, [_P, _I, _I, _I, _I64, _P, _I, _I64, _U, _U, _P]),
     "fht_range": (_I, [_P, _I, _I, _I, _I64, _I, _I, _I, _P, _I, _I64, _P, _SZ, _P]),
     "fht_shift": (_I, [_P, _I64, _P, _I64, _I, _I, _I, _I, _P]),
     "fht_adjoint": (_I, [_P, _I, _I64, _P, _I64, _I, _I, _U, _U, _P, _SZ, _P]),
@@ -257,6 +258,31 @@ def forward(img: torch.Tensor, quads="full", shifted: bool = False, out: torch.T
                            flags, workspace.data_ptr(),
                            workspace.numel() * workspace.element_size(), _stream())
     _check(rc, "fht_forward")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # FHT_NOALLOC_SCRATCH_BYTES
+
+
+def forward_noalloc(img: torch.Tensor, out: torch.Tensor, quads="full", shifted: bool = False,
+                    op: str = "sum") -> torch.Tensor:
+    """forward() through fht_forward_noalloc: no workspace, the library's own
+    per-device scratch array (transforms needing more than
+    NOALLOC_SCRATCH_BYTES raise ValueError).  The caller passes `out`; calls
+    that overlap in time on one GPU race on the shared scratch."""
+    if op not in ("sum", "max"):
+        raise ValueError("op must be 'sum' or 'max'")
+    _check_2d(img, "img")
+    h, w = img.shape
+    it, at, odt = _dtypes(img.dtype)
+    q = _quads(quads)
+    rows, cols = hough_shape(w, h, q)
+    _check_2d(out, "out", (rows, cols), odt)
+    flags = (FHT_FLAG_SHIFTED if shifted else 0) | (FHT_FLAG_MAX if op == "max" else 0)
+    _check_device(img=img, out=out)
+    rc = lib().fht_forward_noalloc(img.data_ptr(), it, w, h, img.stride(0), out.data_ptr(), at, out.stride(0), q,
+                                   flags, _stream())
+    _check(rc, "fht_forward_noalloc")
     return out
 
 
