@@ -6,7 +6,9 @@ image of 16381 x 8192 float32) of a synthetic, seeded image already resident
 in HBM.  Prints one JSON line:
   value         input Gpixels/s of the forward (4096^2 pixels per step)
   roofline      the dominant kernel (last pass) against the 8 TB/s HBM roof:
-                its algorithmic bytes per launch over its average launch time,
+                the transform's compulsory bytes (image once + Hough image
+                once; one launch completes one transform) over its average
+                launch time,
                 measured with HIP events on its launch stream in the timed
                 region; traffic = HBM bytes per launch from the committed
                 counter summary (null when the kernel sources have changed)
@@ -68,6 +70,24 @@ def committed_traffic(kernel: str):
         return None
 
 
+def committed_forward_traffic():
+    """Counter bytes of one whole forward (every pass kernel) from the
+    committed summary, or None when absent or taken on other sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return int(float(kv["forward_traffic_bytes"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def _timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -96,19 +116,27 @@ def last_pass_algorithmic_bytes(fht, w: int, h: int, elem: int) -> int:
     return total + rows * cols * elem
 
 
-def cpu_baseline(img, target_s: float = 10.0):
-    """The CPU oracle (float64 stage recurrence, OpenMP over rows) on the same
-    4096^2 image: repeated full transforms until about target_s seconds."""
+def cpu_baseline(img, reps: int = 3):
+    """The CPU oracle (stage recurrence, OpenMP over rows) on the same 4096^2
+    image: `reps` full transforms in float64 (the oracle's own precision; the
+    reported value) and `reps` in its float32 mode, median of each."""
+    import statistics
+
     import oracle
 
     x = img.astype("float64")
-    reps, total = 0, 0.0
-    while total < target_s and reps < 8:
-        t = time.perf_counter()
-        oracle.full(x)
-        total += time.perf_counter() - t
-        reps += 1
-    px = x.shape[0] * x.shape[1] * reps
+
+    def median_s(single):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            oracle.full(x, single=single)
+            ts.append(time.perf_counter() - t)
+        return statistics.median(ts), sum(ts)
+
+    t64, tot64 = median_s(False)
+    t32, tot32 = median_s(True)
+    px = x.shape[0] * x.shape[1]
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -117,9 +145,12 @@ def cpu_baseline(img, target_s: float = 10.0):
                 break
     except OSError:
         pass
-    return {"value": round(px / total / 1e9, 6), "unit": "Gpixels/s", "cores": oracle.threads(),
+    return {"value": round(px / t64 / 1e9, 6), "unit": "Gpixels/s", "cores": oracle.threads(),
             "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
-            "sample": "%d full float64 transform(s) of the same 4096x4096 image, %.1f s" % (reps, total)}
+            "fp32": {"value": round(px / t32 / 1e9, 6), "unit": "Gpixels/s", "median_s": round(t32, 4)},
+            "median_s": round(t64, 4),
+            "sample": "median of %d full float64 transforms (value) and of %d float32-mode transforms of the "
+                      "same 4096x4096 image, %.1f s in total" % (reps, reps, tot64 + tot32)}
 
 
 def log(msg):
@@ -345,27 +376,39 @@ def main():
     compulsory = px * 4 + rows * cols * 4
     result["hbm_compulsory_frac"] = round(compulsory / (ms_fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
-    # dominant kernel: the largest summed launch time with every kernel timed
+    # dominant kernel: the largest summed launch time with every kernel timed.
+    # Its algorithmic bytes are the whole transform's compulsory traffic (the
+    # image read once, the Hough image written once): one launch of the last
+    # pass completes one transform.  The pass's own bytes (bands in, Hough
+    # image out) are reported beside it.
     name = dominant
     launches, total_ms = kernels[name]
     avg_ms = total_ms / launches
-    alg = last_pass_algorithmic_bytes(fht, side, side, 4)
-    if "fht_pass_kernel<float, float, 3, false, true, 0>" not in name:
-        alg = None  # the byte formula below is that kernel's
+    alg = compulsory if "fht_pass_kernel<float, float, 3, false, true, 0>" in name else None
+    pass_bytes = last_pass_algorithmic_bytes(fht, side, side, 4) if alg else None
     achieved = alg / (avg_ms * 1e-3) / 1e9 if alg else None
+    traffic = committed_traffic(name)
     result["roofline"] = {
         "bound": "hbm",
         "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": committed_traffic(name),
+        "traffic": traffic,
         "kernel": name,
         "launch_ms": round(avg_ms, 4),
         "launches": launches,
         "algorithmic_bytes_per_launch": alg,
+        "algorithmic_bytes": "image once + Hough image once (4096^2 x 4 B + 16381 x 8192 x 4 B)",
+        "pass_bytes_per_launch": pass_bytes,
+        "pass_frac": round(pass_bytes / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if pass_bytes else None,
+        "traffic_over_algorithmic": round(traffic / alg, 3) if (traffic and alg) else None,
         "kernel_times_ms": {k: round(v[1] / v[0], 4) for k, v in kernels_all.items()},
     }
+    forward_traffic = committed_forward_traffic()
+    if forward_traffic:
+        result["forward_traffic_bytes"] = forward_traffic
+        result["forward_traffic_over_compulsory"] = round(forward_traffic / compulsory, 3)
 
     if not args.fwd_only:
         g = torch.empty_like(out).normal_()
