@@ -602,9 +602,10 @@ int fht_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, size_t
 }
 
 // Adjoint workspace: the bands, then one h x w scratch image (row pitch w)
-// per selected quadrant after the first: the image passes of all quadrants
-// run together, each writing its own image, and a final kernel sums them
-// into the gradient in quadrant order.
+// per selected quadrant after the first: the image passes of those quadrants
+// run together, each writing its own scratch image, and the first quadrant's
+// image pass then adds them to its own values in quadrant order as it stores
+// the gradient.
 static size_t scratch_image_bytes(int w, int h) { return ((size_t)w * (size_t)h * 4 + 255) / 256 * 256; }
 
 static size_t adjoint_workspace(QuadGeom* gs, const int* qs, int nq, int w, int h)
@@ -908,72 +909,85 @@ int run_adjoint(const AdjImage* ims, int m, int t, int64_t ld_hough, int64_t ld_
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
     const size_t bands = layout_bands(gs, nq, 4, 0);
-    // image targets: the first quadrant writes the gradient, every later one
-    // its own scratch image; the scratch images are added to the gradient at
-    // the end in quadrant order, so the sum is ((q1 + q2) + q3) + q4
+    // image targets: every quadrant after the first writes its own scratch
+    // image; the first quadrant's image pass runs last, reads them at its
+    // output cells and stores ((q1 + q2) + q3) + q4, the contributions in
+    // quadrant order
     AdjDesc descs[kStackGroup][4][4];
-    const void* scratch_list[kStackGroup][3];
-    int n_scratch = 0;
+    const int last = 0;  // the quadrant whose image pass runs last
     for (int k = 0; k < m; ++k) {
         unsigned char* scratch = ims[k].ws + bands;
-        n_scratch = 0;
+        const void* parts[3] = {nullptr, nullptr, nullptr};
+        int n_part = 0;
         for (int i = 0; i < nq; ++i) {
             void* target = ims[k].img;
             int64_t target_ld = ld_img;
             if (i > 0) {
                 target = scratch;
                 target_ld = w;
-                scratch_list[k][n_scratch++] = scratch;
+                parts[n_part++] = scratch;
                 scratch += scratch_image_bytes(w, h);
             }
             int base, sign, skip, ra, rb;
             placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
-            for (int p = 0; p < gs[i].npass; ++p)
-                descs[k][i][p] = make_adj_desc(gs[i], p, ims[k].grad, ld_hough, target, target_ld, w, h, ims[k].ws,
-                                               base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
+            for (int p = 0; p < gs[i].npass; ++p) {
+                AdjDesc& d = descs[k][i][p];
+                d = make_adj_desc(gs[i], p, ims[k].grad, ld_hough, target, target_ld, w, h, ims[k].ws, base, sign,
+                                  skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
+            }
+        }
+        if (nq > 1) {
+            AdjDesc& d = descs[k][0][0];
+            d.accumulate = 1;
+            d.n_part = n_part;
+            d.part_ld = w;
+            for (int j = 0; j < 3; ++j) d.part[j] = parts[j];
         }
     }
     int maxp = 0;
     for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
     // adjoint passes in reverse order, every image's and quadrant's pass of
-    // one kind in one launch; then the direct (tiny) quadrants and the sums
-    for (int p = maxp - 1; p >= 0; --p) {
+    // one kind in one launch, except the first quadrant's image pass; then
+    // the other direct (tiny) quadrants; then the first quadrant's image
+    // pass, once every other contribution is in place
+    auto launch_kind = [&](int p, bool only_last) -> int {
         for (int G = 3; G <= kMaxG; ++G) {
             for (int first = 0; first < 2; ++first) {
                 AdjLaunch L{};
                 for (int k = 0; k < m; ++k)
-                    for (int i = 0; i < nq; ++i)
+                    for (int i = 0; i < nq; ++i) {
+                        if (p == 0 && (i == last) != only_last) continue;
                         if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G &&
                             (p == gs[i].npass - 1) == (first == 1))
                             L.d[L.nd++] = descs[k][i][p];
+                    }
                 if (L.nd == 0) continue;
                 hipError_t e = launch_adjoint_pass(L, t, s);
                 if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
             }
         }
-        if (p > 0) continue;
-        for (int k = 0; k < m; ++k)
-            for (int i = 0; i < nq; ++i) {
-                if (gs[i].k > 2) continue;
-                AdjLaunch L{};
-                L.d[0] = descs[k][i][0];
-                L.nd = 1;
-                hipError_t e = launch_adjoint_direct(L, gs[i].k, t, s);
-                if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
-            }
-        if (n_scratch > 0) {
-            hipError_t e;
-            if (m == 1) {
-                e = launch_sum_images(ims[0].img, ld_img, scratch_list[0], n_scratch, w, h, t, s);
-            } else {
-                void* imgs[kStackGroup];
-                for (int k = 0; k < m; ++k) imgs[k] = ims[k].img;
-                e = launch_sum_images_multi(imgs, ld_img, scratch_list, m, n_scratch, w, h, t, s);
-            }
-            if (e != hipSuccess) return hip_fail(e, "adjoint sum launch");
+        return FHT_OK;
+    };
+    auto launch_direct_of = [&](int i) -> int {
+        for (int k = 0; k < m; ++k) {
+            AdjLaunch L{};
+            L.d[0] = descs[k][i][0];
+            L.nd = 1;
+            hipError_t e = launch_adjoint_direct(L, gs[i].k, t, s);
+            if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
         }
+        return FHT_OK;
+    };
+    for (int p = maxp - 1; p >= 0; --p) {
+        int rc = launch_kind(p, false);
+        if (rc) return rc;
     }
-    return FHT_OK;
+    for (int i = 1; i < nq; ++i) {
+        if (gs[i].k > 2) continue;
+        int rc = launch_direct_of(i);
+        if (rc) return rc;
+    }
+    return gs[last].k > 2 ? launch_kind(0, true) : launch_direct_of(last);
 }
 
 }  // namespace fht

@@ -392,6 +392,10 @@ __device__ __forceinline__ void patch_band_row(const T* band_row, int src_bw, in
 }
 
 // Image row R of quadrants 1, 2 (x = +-xi, sheared for the angle range).
+// The 8 values arrive in memory order; a mirrored row is reversed by the
+// caller once every row's loads are issued (reversing here, behind the
+// runtime mirror flag, made each row wait for its own loads before the next
+// row's were issued).
 template <typename TIn, typename T>
 __device__ __forceinline__ bool issue_image_row(const PassDesc& d, int R, int xrow, int lane, T (&v)[8], int& e0)
 {
@@ -402,7 +406,6 @@ __device__ __forceinline__ bool issue_image_row(const PassDesc& d, int R, int xr
     const bool fast = row_ok && e0 + 8 <= d.img_w;
     const bool zero = !row_ok || (e0 >= d.img_w && e0 + 8 <= W);
     load8_src<TIn, T>(fast ? p + e0 : zero_page<TIn>(), v);
-    if (d.mirror) reverse8(v);
     return !fast && !zero;
 }
 
@@ -626,20 +629,57 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
             bool patch[8];
             bool any = false;
             const T* band = reinterpret_cast<const T*>(d.src);
+            // The source kind is chosen once for all rows: a choice per row
+            // ends every row in a merge of two paths, where the register
+            // moves wait for that row's loads before the next row's issue.
+            const bool vector_rows = !FIRST || (d.src_kind == SRC_IMAGE && d.scale_num == 0);
+            if (FIRST && vector_rows && d.S1 == 0) {
+                // first pass without a shear: the wave's 8 rows are consecutive
+                // image rows read at the same columns, so the lane's column
+                // run is computed once
+                const int R0 = (B << G) + (tr0 & ((1 << G) - 1));
+                const int ec = lane_run_start(xi0, 0, lane, d.W, d.mirror);
+                const bool col_fast = ec + 8 <= d.img_w;
+                const bool col_zero = ec >= d.img_w && ec + 8 <= d.W;
+                const TIn* p = reinterpret_cast<const TIn*>(d.src) + (long long)R0 * d.src_ld + ec;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int m = (tr0 + r) & ((1 << G) - 1);
-                const int R = (B << (j0 + G)) + (m << j0) + u;
-                if constexpr (FIRST) {
-                    // scaled sources take the element path
-                    patch[r] = (d.src_kind == SRC_IMAGE && d.scale_num == 0)
-                                   ? issue_image_row<TIn, T>(d, R, xi0, lane, a[r], e0[r])
-                                   : issue_image_t_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
-                } else {
-                    patch[r] = issue_band_row<T>(band + (long long)R * d.src_ld, d.src_off, d.src_bw, d.W,
-                                                 xi0 + u * m, lane, a[r], e0[r]);
+                for (int r = 0; r < 8; ++r) {
+                    const bool row_ok = R0 + r < d.img_h;
+                    const bool fast = row_ok && col_fast;
+                    load8_src<TIn, T>(fast ? p + (long long)r * d.src_ld : zero_page<TIn>(), a[r]);
+                    e0[r] = ec;
+                    patch[r] = row_ok && !col_fast && !col_zero;
+                    any |= patch[r];
                 }
-                any |= patch[r];
+                if (d.mirror) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) reverse8(a[r]);
+                }
+            } else if (vector_rows) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int m = (tr0 + r) & ((1 << G) - 1);
+                    const int R = (B << (j0 + G)) + (m << j0) + u;
+                    if constexpr (FIRST)
+                        patch[r] = issue_image_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
+                    else
+                        patch[r] = issue_band_row<T>(band + (long long)R * d.src_ld, d.src_off, d.src_bw, d.W,
+                                                     xi0 + u * m, lane, a[r], e0[r]);
+                    any |= patch[r];
+                }
+                if (FIRST && d.mirror) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) reverse8(a[r]);
+                }
+            } else {
+                // transposed sheared or scaled sources: the element path
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int m = (tr0 + r) & ((1 << G) - 1);
+                    const int R = (B << (j0 + G)) + (m << j0) + u;
+                    patch[r] = issue_image_t_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
+                    any |= patch[r];
+                }
             }
             if (__any(any)) {
 #pragma unroll
@@ -827,7 +867,8 @@ __global__ __launch_bounds__(kThreads, 4) void fht_engine_kernel(const EngineArg
 // u*m added.  The halo sits at the low end of the tile.
 
 // Hough gradient row (first adjoint pass): quadrant row s -> Hough row, x =
-// +-xi, rolled columns.
+// +-xi, rolled columns.  Values arrive in memory order; the caller reverses
+// mirrored rows after every row's loads are issued.
 template <typename T>
 __device__ __forceinline__ bool adj_issue_hough(const AdjDesc& d, int s_row, int xrow, int lane, T (&v)[8], int& e0)
 {
@@ -845,7 +886,6 @@ __device__ __forceinline__ bool adj_issue_hough(const AdjDesc& d, int s_row, int
     }
     const bool fast = !skip && !black && e0 + 8 <= W;
     load8<T>(fast ? src + e0 : zero_page<T>(), v);
-    if (d.mirror) reverse8(v);
     return !skip && !black && !fast;
 }
 
@@ -857,19 +897,41 @@ __device__ __forceinline__ void adj_patch_hough(const AdjDesc& d, int s_row, int
     for (int c = 0; c < 8; ++c) v[c] = src[run_col(e0, c, d.W, d.mirror)];
 }
 
+// Image-gradient stores.  Without accumulate the value is written; with it
+// the result is ((value + part[0]) + part[1]) + part[2]: this quadrant's
+// contribution first, then the other quadrants' partial images in quadrant
+// order (pi: the element's index in the partial images).  Every partial is
+// loaded before the first add, so the loads of a row go out together.
 template <typename T>
-__device__ __forceinline__ void acc_store8(T* p, const T (&v)[8], bool accumulate)
+__device__ __forceinline__ void acc_store8(const AdjDesc& d, T* p, int64_t pi, const T (&v)[8])
 {
-    if (accumulate) {
-        T o[8];
-        load8<T>(p, o);
-        T s[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) s[c] = o[c] + v[c];
-        store8<T>(p, s);
-    } else {
+    if (!d.accumulate) {
         store8<T>(p, v);
+        return;
     }
+    T t0[8], t1[8], t2[8];
+    load8<T>(reinterpret_cast<const T*>(d.part[0]) + pi, t0);
+    if (d.n_part > 1) load8<T>(reinterpret_cast<const T*>(d.part[1]) + pi, t1);
+    if (d.n_part > 2) load8<T>(reinterpret_cast<const T*>(d.part[2]) + pi, t2);
+    T o[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) o[c] = v[c] + t0[c];
+    if (d.n_part > 1)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) o[c] = o[c] + t1[c];
+    if (d.n_part > 2)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) o[c] = o[c] + t2[c];
+    store8<T>(p, o);
+}
+
+template <typename T>
+__device__ __forceinline__ T acc_value(const AdjDesc& d, int64_t pi, T v)
+{
+    if (!d.accumulate) return v;
+    T o = v;
+    for (int k = 0; k < d.n_part; ++k) o = o + reinterpret_cast<const T*>(d.part[k])[pi];
+    return o;
 }
 
 template <typename T, int GB>
@@ -956,6 +1018,10 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
             }
             any |= patch[rho];
         }
+        if (first && d.mirror) {
+#pragma unroll
+            for (int rho = 0; rho < 8; ++rho) reverse8(b[rho]);
+        }
         if (__any(any)) {
 #pragma unroll
             for (int rho = 0; rho < 8; ++rho) {
@@ -1035,12 +1101,13 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
                 T v[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) v[c] = d.mirror ? a[r][7 - c] : a[r][c];
-                acc_store8<T>(p + e0, v, d.accumulate != 0);
+                acc_store8<T>(d, p + e0, (int64_t)R * d.part_ld + e0, v);
             } else {
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int e = run_col(e0, c, W, d.mirror);
-                    if (rel + c < cols && e < cols) p[e] = d.accumulate ? (T)(p[e] + a[r][c]) : a[r][c];
+                    if (rel + c < cols && e < cols)
+                        p[e] = acc_value<T>(d, (int64_t)R * d.part_ld + e, a[r][c]);
                 }
             }
         }
@@ -1056,12 +1123,13 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
             T v[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) v[r] = a[r][c];
+            const int64_t pi = (int64_t)e * d.part_ld + R0;
             if (all_cols) {
-                acc_store8<T>(p, v, d.accumulate != 0);
+                acc_store8<T>(d, p, pi, v);
             } else {
 #pragma unroll
                 for (int r = 0; r < 8; ++r)
-                    if (R0 + r < d.img_w) p[r] = d.accumulate ? (T)(p[r] + v[r]) : v[r];
+                    if (R0 + r < d.img_w) p[r] = acc_value<T>(d, pi + r, v[r]);
             }
         }
     }
@@ -1187,79 +1255,8 @@ __global__ __launch_bounds__(256) void fht_adj_direct_kernel(const AdjLaunch L)
     const T v = adj_direct<T, 0, K>(d, R, x);
     T* p = d.dst_kind == 2 ? reinterpret_cast<T*>(d.dst) + (long long)x * d.dst_ld + R
                            : reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x;
-    *p = d.accumulate ? (T)(*p + v) : v;
-}
-
-// ------------------------------------------------ adjoint quadrant sum
-
-// The adjoint's per-quadrant images added in quadrant order (consecutive x
-// per thread, four at a time when rows are 16-byte aligned):
-// img = ((img + s0) + s1) + s2.
-template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void fht_sum_images_kernel(T* img, int64_t ld_img, const T* s0, const T* s1,
-                                                             const T* s2, int n, int w, int h)
-{
-    constexpr int V = VEC ? 4 : 1;
-    const int x = (blockIdx.x * blockDim.x + threadIdx.x) * V;
-    if (x >= w) return;
-    for (int y = blockIdx.y; y < h; y += gridDim.y) {  // grid y capped at 65535
-        const int64_t i = (int64_t)y * w + x;
-        T* p = img + (int64_t)y * ld_img + x;
-        if constexpr (VEC) {
-            typedef typename vec4u<T>::type V4;
-            V4 v = *reinterpret_cast<const V4*>(p);
-            v = v + *reinterpret_cast<const V4*>(s0 + i);
-            if (n > 1) v = v + *reinterpret_cast<const V4*>(s1 + i);
-            if (n > 2) v = v + *reinterpret_cast<const V4*>(s2 + i);
-            *reinterpret_cast<V4*>(p) = v;
-        } else {
-            T v = *p;
-            v = v + s0[i];
-            if (n > 1) v = v + s1[i];
-            if (n > 2) v = v + s2[i];
-            *p = v;
-        }
-    }
-}
-
-// The same for up to kSumSet images of one size in one launch (blockIdx.z).
-constexpr int kSumSet = 4;
-template <typename T>
-struct SumSet {
-    T* img[kSumSet];
-    const T* s[kSumSet][3];
-};
-
-template <typename T, int VEC>
-__global__ __launch_bounds__(256) void fht_sum_images_multi_kernel(const SumSet<T> set, int64_t ld_img, int n, int w,
-                                                                   int h)
-{
-    constexpr int V = VEC ? 4 : 1;
-    const int z = blockIdx.z;
-    const int x = (blockIdx.x * blockDim.x + threadIdx.x) * V;
-    if (x >= w) return;
-    T* img = set.img[z];
-    const T* s0 = set.s[z][0];
-    const T* s1 = set.s[z][1];
-    const T* s2 = set.s[z][2];
-    for (int y = blockIdx.y; y < h; y += gridDim.y) {  // grid y capped at 65535
-        const int64_t i = (int64_t)y * w + x;
-        T* p = img + (int64_t)y * ld_img + x;
-        if constexpr (VEC) {
-            typedef typename vec4u<T>::type V4;
-            V4 v = *reinterpret_cast<const V4*>(p);
-            v = v + *reinterpret_cast<const V4*>(s0 + i);
-            if (n > 1) v = v + *reinterpret_cast<const V4*>(s1 + i);
-            if (n > 2) v = v + *reinterpret_cast<const V4*>(s2 + i);
-            *reinterpret_cast<V4*>(p) = v;
-        } else {
-            T v = *p;
-            v = v + s0[i];
-            if (n > 1) v = v + s1[i];
-            if (n > 2) v = v + s2[i];
-            *p = v;
-        }
-    }
+    const int64_t pi = d.dst_kind == 2 ? (int64_t)x * d.part_ld + R : (int64_t)R * d.part_ld + x;
+    *p = acc_value<T>(d, pi, v);
 }
 
 // ------------------------------------------------ angle-range adjoint tail

@@ -74,7 +74,10 @@ struct AdjDesc {
     int64_t src_ld, dst_ld;
     int src_kind;         // 0: Hough rows, 1: band
     int dst_kind;         // 0: band, 1: image, 2: image transposed
-    int accumulate;       // image destinations: add to the existing value
+    int accumulate;       // image destination: 1 = store ((value + part[0]) + part[1]) + part[2]
+    int n_part;           //   over the first n_part (1..3) partial images (the other
+    int64_t part_ld;      //   quadrants' contributions, image layout h x w, row pitch
+    const void* part[3];  //   part_ld); 0 = store the value
     int img_w, img_h;
     int n, W, j0, G, mirror;
     int src_off, src_bw;
@@ -134,14 +137,6 @@ hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s);
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,
                         int hp, int wp, int inverse, hipStream_t s);
-// img[y, x] = ((img + s[0]) + s[1]) + ... over n (1..3) scratch images of
-// h x w, row pitch w; t = 1 (int32) or 2 (float32).
-hipError_t launch_sum_images(void* img, int64_t ld_img, const void* const* scr, int n, int w, int h, int t,
-                             hipStream_t s);
-// The same for m (1..4) images of one size in one launch: imgs[k] and
-// scr[k][0..n-1] belong to image k.
-hipError_t launch_sum_images_multi(void* const* imgs, int64_t ld_img, const void* const (*scr)[3], int m, int n, int w,
-                                   int h, int t, hipStream_t s);
 // Angle-range adjoint, last step: img[y, x] = a0[r, (c + sigma(r)) mod W]
 // (r, c) = (y, x), or (x, y) when transposed; a0 is n x W, row pitch W.
 hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,

@@ -136,62 +136,6 @@ hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem
     return hipGetLastError();
 }
 
-template <typename T>
-static void launch_sum_t(T* img, int64_t ld_img, const void* const* scr, int n, int w, int h, hipStream_t s)
-{
-    const T* a = (const T*)scr[0];
-    const T* b = (const T*)scr[n > 1 ? 1 : 0];
-    const T* c = (const T*)scr[n > 2 ? 2 : 0];
-    const bool vec = (w % 4 == 0) && (ld_img % 4 == 0) && (((uintptr_t)img & 15) == 0);
-    const int gy = h < 65535 ? h : 65535;
-    if (vec)
-        hipLaunchKernelGGL((fht_sum_images_kernel<T, true>), dim3((w / 4 + 255) / 256, gy), dim3(256), 0, s, img, ld_img,
-                           a, b, c, n, w, h);
-    else
-        hipLaunchKernelGGL((fht_sum_images_kernel<T, false>), dim3((w + 255) / 256, gy), dim3(256), 0, s, img, ld_img,
-                           a, b, c, n, w, h);
-}
-
-hipError_t launch_sum_images(void* img, int64_t ld_img, const void* const* scr, int n, int w, int h, int t,
-                             hipStream_t s)
-{
-    if (n < 1 || n > 3) return hipErrorInvalidValue;
-    if (t == 2) launch_sum_t<float>((float*)img, ld_img, scr, n, w, h, s);
-    else if (t == 1) launch_sum_t<int>((int*)img, ld_img, scr, n, w, h, s);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-template <typename T>
-static void launch_sum_multi_t(void* const* imgs, int64_t ld_img, const void* const (*scr)[3], int m, int n, int w,
-                               int h, hipStream_t s)
-{
-    SumSet<T> set{};
-    bool vec = (w % 4 == 0) && (ld_img % 4 == 0);
-    for (int k = 0; k < m; ++k) {
-        set.img[k] = (T*)imgs[k];
-        for (int j = 0; j < 3; ++j) set.s[k][j] = (const T*)scr[k][j < n ? j : 0];
-        vec = vec && (((uintptr_t)imgs[k] & 15) == 0);
-    }
-    const int gy = h < 65535 ? h : 65535;
-    if (vec)
-        hipLaunchKernelGGL((fht_sum_images_multi_kernel<T, true>), dim3((w / 4 + 255) / 256, gy, m), dim3(256), 0, s,
-                           set, ld_img, n, w, h);
-    else
-        hipLaunchKernelGGL((fht_sum_images_multi_kernel<T, false>), dim3((w + 255) / 256, gy, m), dim3(256), 0, s,
-                           set, ld_img, n, w, h);
-}
-
-hipError_t launch_sum_images_multi(void* const* imgs, int64_t ld_img, const void* const (*scr)[3], int m, int n, int w,
-                                   int h, int t, hipStream_t s)
-{
-    if (n < 1 || n > 3 || m < 1 || m > kSumSet) return hipErrorInvalidValue;
-    if (t == 2) launch_sum_multi_t<float>(imgs, ld_img, scr, m, n, w, h, s);
-    else if (t == 1) launch_sum_multi_t<int>(imgs, ld_img, scr, m, n, w, h, s);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
 hipError_t launch_unshear(const void* a0, int W, int n, int S1, void* img, int64_t ld_img, int w, int h,
                           int transposed, int elem_bytes, hipStream_t s)
 {
