@@ -727,7 +727,9 @@ __global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch 
         t -= L.d[z].n_row_tiles * L.d[z].n_windows;
         ++z;
     }
-    const PassDesc& d = L.d[z];
+    // a private copy of the descriptor: a reference into the arguments at a
+    // dynamic index had every stored row read its fields again
+    const PassDesc d = L.d[z];
     const int rt = t / d.n_windows;
     fwd_tile<TIn, T, GB, FIRST, LAST, OP>(d, rt, t - rt * d.n_windows, lds);
 }
@@ -747,10 +749,12 @@ __global__ __launch_bounds__(kThreads, 4) void fht_table_kernel(const EngineGrou
         if (table[mid].first_item <= item) lo = mid;
         else hi = mid - 1;
     }
-    const EngineGroup& E = table[uniform(lo)];
-    const int local = item - E.first_item;
-    const int rt = local / E.d.n_windows;
-    fwd_tile<TIn, T, GB, FIRST, LAST>(E.d, rt, local - rt * E.d.n_windows, lds);
+    // a private copy of the descriptor: read once, its fields stay in
+    // registers (the table is global memory, which every store could alias)
+    const PassDesc d = table[uniform(lo)].d;
+    const int local = item - table[uniform(lo)].first_item;
+    const int rt = local / d.n_windows;
+    fwd_tile<TIn, T, GB, FIRST, LAST>(d, rt, local - rt * d.n_windows, lds);
 }
 
 // ------------------------------------------------- persistent forward engine
@@ -929,8 +933,11 @@ template <typename T>
 __device__ __forceinline__ T acc_value(const AdjDesc& d, int64_t pi, T v)
 {
     if (!d.accumulate) return v;
-    T o = v;
-    for (int k = 0; k < d.n_part; ++k) o = o + reinterpret_cast<const T*>(d.part[k])[pi];
+    // fixed indices: a loop over part[k] would index the descriptor
+    // dynamically and move it to scratch memory
+    T o = v + reinterpret_cast<const T*>(d.part[0])[pi];
+    if (d.n_part > 1) o = o + reinterpret_cast<const T*>(d.part[1])[pi];
+    if (d.n_part > 2) o = o + reinterpret_cast<const T*>(d.part[2])[pi];
     return o;
 }
 
@@ -1139,7 +1146,7 @@ template <typename T, int GB, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kThreads, 4) void fht_adj_pass_kernel(const AdjLaunch L)
 {
     __shared__ T lds[kTileRows / 2 * kLdsRow];
-    const AdjDesc& d = L.d[blockIdx.z];
+    const AdjDesc d = L.d[blockIdx.z];  // a private copy: its fields stay in registers across the stores
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
     adj_tile<T, GB, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
 }
