@@ -76,6 +76,16 @@ template <typename T> __device__ __forceinline__ T to_acc(float v) { return (T)v
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Storage row of quadrant row R in an intermediate band written after j of
+// the k stages.  Row R = (b << j) + v (block b, row v of the block) is stored
+// at (v << (k - j)) + b: the next pass reads rows (m << j) + u for 2^G
+// consecutive m, which land on consecutive storage rows (one contiguous run
+// instead of rows 2^j apart).  Writer and reader use the same j.
+__device__ __forceinline__ int band_row(int R, int j, int k)
+{
+    return ((R & ((1 << j) - 1)) << (k - j)) + (R >> j);
+}
+
 // a mod W for a wave-uniform a (|a| < 4W whenever W >= 1024 in the pass
 // geometry; small W takes the division).
 __device__ __forceinline__ int mod_w(int a, int W)
@@ -370,24 +380,24 @@ __device__ __forceinline__ void lds_write8(T* row_lane, int off, const T (&v)[8]
 
 // Band row at xi = xrow + 8*lane + c (band index = (xi + src_off) mod W).
 template <typename T>
-__device__ __forceinline__ bool issue_band_row(const T* band_row, int src_off, int src_bw, int W, int xrow, int lane,
+__device__ __forceinline__ bool issue_band_row(const T* row_ptr, int src_off, int src_bw, int W, int xrow, int lane,
                                                T (&v)[8], int& e0)
 {
     e0 = wrap_up(mod_w(xrow + src_off, W) + 8 * lane, W);
     const bool fast = e0 + 8 <= src_bw;
     const bool zero = e0 >= src_bw && e0 + 8 <= W;
-    load8<T>(fast ? band_row + e0 : zero_page<T>(), v);
+    load8<T>(fast ? row_ptr + e0 : zero_page<T>(), v);
     return !fast && !zero;
 }
 
 template <typename T>
-__device__ __forceinline__ void patch_band_row(const T* band_row, int src_bw, int W, int e0, T (&v)[8])
+__device__ __forceinline__ void patch_band_row(const T* row_ptr, int src_bw, int W, int e0, T (&v)[8])
 {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         int e = e0 + c;
         if (e >= W) e -= W;
-        v[c] = (e < src_bw) ? band_row[e] : (T)0;
+        v[c] = (e < src_bw) ? row_ptr[e] : (T)0;
     }
 }
 
@@ -546,7 +556,8 @@ __device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, in
         if (s_local > d.row_limit) continue;
         const int out_row = (B << (j0 + G)) + s_local;
         if constexpr (!LAST) {
-            T* dst = reinterpret_cast<T*>(d.dst) + (long long)out_row * d.dst_ld;
+            const int k = 31 - __builtin_clz(d.n);
+            T* dst = reinterpret_cast<T*>(d.dst) + (long long)band_row(out_row, j0 + G, k) * d.dst_ld;
             const int e0 = xi + d.dst_off;
             if (e0 + 8 <= d.dst_bw) {
                 store8<T>(dst + e0, b[rho]);
@@ -590,6 +601,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
     const int wave = uniform(threadIdx.x >> 6);
     const int j0 = d.j0;
     const int n_mini = d.n >> G;                 // mini-transforms in the quadrant
+    const int k = 31 - __builtin_clz(d.n);       // stages of the quadrant
     const int xi0 = d.x_start + win * VW;        // xi of the tile's column 0
 
     // A last-pass tile lying wholly in the black zone of every one of its rows
@@ -663,8 +675,8 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                     if constexpr (FIRST)
                         patch[r] = issue_image_row<TIn, T>(d, R, xi0, lane, a[r], e0[r]);
                     else
-                        patch[r] = issue_band_row<T>(band + (long long)R * d.src_ld, d.src_off, d.src_bw, d.W,
-                                                     xi0 + u * m, lane, a[r], e0[r]);
+                        patch[r] = issue_band_row<T>(band + (long long)band_row(R, j0, k) * d.src_ld, d.src_off,
+                                                     d.src_bw, d.W, xi0 + u * m, lane, a[r], e0[r]);
                     any |= patch[r];
                 }
                 if (FIRST && d.mirror) {
@@ -688,7 +700,8 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                         const int m = (tr0 + r) & ((1 << G) - 1);
                         const int R = (B << (j0 + G)) + (m << j0) + u;
                         if constexpr (FIRST) patch_image_row<TIn, T>(d, R, e0[r], a[r]);
-                        else patch_band_row<T>(band + (long long)R * d.src_ld, d.src_bw, d.W, e0[r], a[r]);
+                        else patch_band_row<T>(band + (long long)band_row(R, j0, k) * d.src_ld, d.src_bw, d.W, e0[r],
+                                               a[r]);
                     }
                 }
             }
