@@ -60,9 +60,8 @@ enum fht_status {
     FHT_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
     FHT_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required */
     FHT_ERR_HIP = -4,         /* a HIP runtime call or launch failed */
-    FHT_ERR_TIMEOUT = -5      /* reserved; the opt-in persistent engine (FHT_ENGINE=1)
-                                 records an expired dependency wait as a nonzero
-                                 word 1 of the workspace instead */
+    FHT_ERR_TIMEOUT = -5      /* fht_engine_status: a bounded dependency wait of the
+                                 opt-in persistent engine (FHT_ENGINE=1) gave up */
 };
 
 enum fht_dtype { FHT_U8 = 0, FHT_I32 = 1, FHT_F32 = 2 };
@@ -342,6 +341,19 @@ int fht_timing_report(int index, char* name, int name_cap, int64_t* launches, do
  */
 int fht_set_pass_split(int k, int npass, const int* passes);
 int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream);
+
+/*
+ * Error state of the opt-in persistent engine (environment FHT_ENGINE=1 at
+ * the first call in the process): a forward call run by the engine waits
+ * for the tiles of a quadrant's previous pass with a bounded spin
+ * (FHT_SPIN_LIMIT iterations, default 2^21) and, if a wait gives up, marks
+ * word 1 of its workspace and carries on, so the kernel always ends.  This
+ * call waits for `stream` and reads that word for the last engine call on
+ * `workspace`: FHT_ERR_TIMEOUT if a wait gave up (that call's results are
+ * invalid), FHT_OK otherwise.  It synchronises the stream; not for the hot
+ * path.  Without the engine the word is never written.
+ */
+int fht_engine_status(const void* workspace, void* stream);
 
 /* Stage-fusion split chosen for a side (number of passes and stages per pass),
  * for inspection and tests.  passes[] receives up to 4 entries. */

@@ -331,6 +331,10 @@ int run_engine(const std::vector<EngineGroup>& groups, const EngineGroup* dev_ta
     (void)dev_table;
     if (groups.empty()) return FHT_OK;
     const int grid_max = engine_grid_size();
+    // word 1 (the error flag) is cleared once per call, so a wait that gave
+    // up in an earlier launch of the call stays visible to fht_engine_status
+    hipError_t ez = launch_zero(sync + 1, 1, 1, 1, 4, stream);
+    if (ez != hipSuccess) return hip_fail(ez, "engine error flag reset");
     for (int G = kMaxG; G >= 3; --G) {
         std::vector<int> remap(groups.size(), -1);
         EngineArgs A{};
@@ -353,7 +357,9 @@ int run_engine(const std::vector<EngineGroup>& groups, const EngineGroup* dev_ta
         A.spin_limit = engine_spin_limit();
         A.agent_acquire = engine_agent_acquire();
         A.table = nullptr;
-        hipError_t e = launch_zero(sync, 1, n + 2, n + 2, 4, stream);
+        // queue head (word 0) and the group counters (words 2..n+1)
+        hipError_t e = launch_zero(sync, 1, 1, 1, 4, stream);
+        if (e == hipSuccess) e = launch_zero(sync + 2, 1, n, n, 4, stream);
         if (e != hipSuccess) return hip_fail(e, "engine counter reset");
         e = launch_engine(A, G, item < grid_max ? item : grid_max, in_t, acc_t, stream);
         if (e != hipSuccess) return hip_fail(e, "engine launch");
@@ -449,6 +455,19 @@ int fht_pass_split(int side, int* npass, int* passes)
     int G[4];
     pass_split(ilog2(pow2_ceil(side)), npass, G);
     for (int i = 0; i < *npass; ++i) passes[i] = G[i];
+    return FHT_OK;
+}
+
+int fht_engine_status(const void* workspace, void* stream)
+{
+    if (!workspace) return fail(FHT_ERR_INVALID, "null workspace");
+    unsigned flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, (const unsigned char*)workspace + 4, sizeof flag, hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the engine's error flag");
+    if (flag) return fail(FHT_ERR_TIMEOUT, "a dependency wait of the persistent engine gave up; the results of that call "
+                                           "are invalid");
     return FHT_OK;
 }
 

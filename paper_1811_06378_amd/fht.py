@@ -76,6 +76,7 @@ SIGNATURES = {
     "fht_range_adjoint": (_I, [_P, _I, _I64, _I, _I, _I, _P, _I64, _I, _I, _P, _SZ, _P]),
     "fht_cell_segment": (_I, [_I, _I, _U, _I64, _I64, _I, _PI32]),
     "fht_peaks": (_I, [_P, _I, _I64, _I64, _I64, _I, ctypes.c_double, _P, _I, _P, _P]),
+    "fht_engine_status": (_I, [_P, _P]),
     "fht_set_pass_split": (_I, [_I, _I, ctypes.POINTER(_I)]),
     "fht_autotune": (_I, [_I, _I, _I, _I, _I, _P]),
     "fht_timing_enable": (_I, [_I]),
@@ -284,6 +285,14 @@ def forward_noalloc(img: torch.Tensor, out: torch.Tensor, quads="full", shifted:
                                    flags, _stream())
     _check(rc, "fht_forward_noalloc")
     return out
+
+
+def engine_status(workspace: torch.Tensor):
+    """Raises FHTError (FHT_ERR_TIMEOUT) if the last call run by the opt-in
+    persistent engine (FHT_ENGINE=1) on this workspace had a dependency wait
+    give up; waits for the current stream."""
+    _check_device(workspace=workspace)
+    _check(lib().fht_engine_status(workspace.data_ptr(), _stream()), "fht_engine_status")
 
 
 def range_params(n: int, deg_lo: float, deg_hi: float):

@@ -137,6 +137,14 @@ def test_validation_before_hip():
     assert L.fht_forward(dummy, 2, 8, 8, 8, dummy, 2, 16, 15, 4, None, 0, s) == fht.FHT_ERR_INVALID
     # fhtshift overlap that is not identity
     assert L.fht_shift(dummy, 16, ctypes.c_void_p(0x1004), 16, 2, 8, 8, 0, s) == fht.FHT_ERR_INVALID
+    # engine status needs the workspace it reads
+    assert L.fht_engine_status(None, s) == fht.FHT_ERR_INVALID
+    # the allocation-free forward validates like fht_forward, and rejects
+    # transforms whose bands exceed its scratch before touching the device
+    assert L.fht_forward_noalloc(None, 2, 8, 8, 8, dummy, 2, 16, 15, 0, s) == fht.FHT_ERR_INVALID
+    assert L.fht_forward_noalloc(dummy, 2, 8, 8, 7, dummy, 2, 16, 15, 0, s) == fht.FHT_ERR_INVALID
+    assert L.fht_forward_noalloc(dummy, 2, 2048, 2048, 2048, dummy, 2, 4096, 15, 0, s) == fht.FHT_ERR_UNSUPPORTED
+    assert b"allocation-free" in L.fht_last_error()
     # batch: bad sizes
     p = ctypes.c_void_p()
     wsb, tot = ctypes.c_size_t(), ctypes.c_int64()

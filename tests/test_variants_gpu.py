@@ -25,7 +25,34 @@ for (h, w, kind) in [(5, 13, "u8"), (129, 257, "u8"), (300, 520, "f32"), (1000, 
 img = synth.random_image(100, 37, "u8", seed=4)
 got = fht.forward(torch.from_numpy(img).cuda(), quads=[2, 3]).cpu().numpy().astype(np.float64)
 assert np.array_equal(got, oracle.stacked_quadrants(img, [2, 3]))
+# no dependency wait gave up
+img = synth.random_image(256, 256, "u8", seed=5)
+ws = torch.empty(fht.workspace_size(256, 256, "full", torch.uint8), dtype=torch.uint8, device="cuda")
+got = fht.forward(torch.from_numpy(img).cuda(), workspace=ws).cpu().numpy().astype(np.float64)
+assert np.array_equal(got, oracle.full(img))
+fht.engine_status(ws)
 print("OK")
+"""
+
+# With a spin limit of 1 iteration, the second-pass tiles of a 256^2 image
+# (two passes of 4 stages, every tile resident at once) give up waiting for
+# the first pass: each wait ends by itself, the flag is set, and the status
+# call reports it.  No kernel hangs or faults; the results are discarded.
+TIMEOUT_CHILD = r"""
+import sys
+sys.path.insert(0, {root!r})
+import torch
+from paper_1811_06378_amd import fht, synth
+img = torch.from_numpy(synth.random_image(256, 256, "u8", seed=5)).cuda()
+ws = torch.empty(fht.workspace_size(256, 256, "full", torch.uint8), dtype=torch.uint8, device="cuda")
+fht.forward(img, workspace=ws)
+try:
+    fht.engine_status(ws)
+except fht.FHTError as e:
+    assert "gave up" in str(e), str(e)
+    print("TIMEOUT REPORTED")
+else:
+    print("NOT REPORTED")
 """
 
 
@@ -35,3 +62,11 @@ def test_variant_matches_oracle(env):
     r = subprocess.run([sys.executable, "-c", code], env={**os.environ, **env}, capture_output=True, text=True,
                        timeout=240)
     assert r.returncode == 0 and r.stdout.strip().endswith("OK"), (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+
+
+def test_engine_reports_expired_waits():
+    code = TIMEOUT_CHILD.format(root=ROOT)
+    env = {**os.environ, "FHT_ENGINE": "1", "FHT_SPIN_LIMIT": "1"}
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and r.stdout.strip().endswith("TIMEOUT REPORTED"), (r.returncode, r.stdout[-2000:],
+                                                                                   r.stderr[-2000:])
