@@ -355,6 +355,21 @@ int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream);
  */
 int fht_engine_status(const void* workspace, void* stream);
 
+/*
+ * Tile height of the pass kernels.  A pass runs on tiles of 64 rows (8
+ * waves, two workgroups per CU) or, for passes of at most 5 stages, 32 rows
+ * (4 waves, half the LDS, four workgroups per CU): twice as many tiles,
+ * which fills the chip at sizes whose passes have few tiles.  Results are
+ * bit-identical either way (the same additions in the same order).  The
+ * default rule is 32 rows for every pass of at most 5 stages.
+ * fht_set_tile_rows sets the height used from now on for passes of at most 5
+ * stages of quadrants with 2^k rows (rows = 32 or 64; 0 restores the default
+ * rule; k in 3..16); passes of 6 stages always use 64.  fht_tile_rows
+ * returns the height such passes use for a side.  fht_autotune also picks it.
+ */
+int fht_set_tile_rows(int k, int rows);
+int fht_tile_rows(int side, int* rows);
+
 /* Stage-fusion split chosen for a side (number of passes and stages per pass),
  * for inspection and tests.  passes[] receives up to 4 entries. */
 int fht_pass_split(int side, int* npass, int* passes);

@@ -53,6 +53,21 @@ int ilog2(int64_t p)
 // the default rule).  Read at planning time only.
 static std::mutex g_split_mu;
 static int g_split[32][5];
+// tile height per k for passes of at most 5 stages (0: the default rule),
+// set by fht_set_tile_rows / fht_autotune; guarded by g_split_mu
+static int g_rows[32];
+
+// Tile height of a pass of G stages of a quadrant with 2^k rows.  Passes of
+// 6 stages need 64-row tiles.  Otherwise 32 unless set for k: twice the
+// tiles and four workgroups per CU measured faster at every size tried
+// (side 128 to 2048, uint8 and float32: 3 to 15 %; the 512-image batch 4 %).
+int tile_rows_for(int k, int G)
+{
+    if (G > 5) return kTileRows;
+    std::lock_guard<std::mutex> lock(g_split_mu);
+    if (k >= 0 && k < 32 && g_rows[k] > 0) return g_rows[k];
+    return kNarrowRows;
+}
 
 static int default_passes(int k) { return (k + kMaxG - 1) / kMaxG; }
 
@@ -219,7 +234,8 @@ PassDesc make_pass_desc(const QuadGeom& g, int p, const void* img, int w, int h,
     d.mirror = g.mirror;
     d.img_w = w;
     d.img_h = h;
-    d.n_row_tiles = (g.n + kTileRows - 1) / kTileRows;
+    d.tile_rows = tile_rows_for(g.k, G);
+    d.n_row_tiles = (g.n + d.tile_rows - 1) / d.tile_rows;
     if (p == 0) {
         d.src = img;
         d.src_ld = ld_img;
@@ -280,6 +296,9 @@ int append_engine_groups(const QuadGeom* gs, const PassDesc (*descs)[4], int nq,
             if (i < 0 || i >= nq || gs[i].k <= 2 || p >= gs[i].npass) continue;
             EngineGroup e{};
             e.d = descs[i][p];
+            // the engine runs 64-row tiles only
+            e.d.tile_rows = kTileRows;
+            e.d.n_row_tiles = (e.d.n + kTileRows - 1) / kTileRows;
             e.first_item = item;
             e.count = e.d.n_row_tiles * e.d.n_windows;
             e.dep = p > 0 ? group_of[i][p - 1] : -1;
@@ -402,14 +421,17 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
     for (int p = 0; p < maxp; ++p) {
         for (int G = kMaxG; G >= 3; --G) {
             for (int last = 0; last < 2; ++last) {
-                PassLaunch L{};
-                for (int i = 0; i < nq; ++i)
-                    if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (last == 1))
-                        L.d[L.nd++] = descs[i][p];
-                if (L.nd == 0) continue;
-                const int ti = p == 0 ? in_t : acc_t;
-                hipError_t e = launch_pass(L, ti, acc_t, stream, op);
-                if (e != hipSuccess) return hip_fail(e, "forward pass launch");
+                for (int rows = kTileRows; rows >= kNarrowRows; rows /= 2) {
+                    PassLaunch L{};
+                    for (int i = 0; i < nq; ++i)
+                        if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G &&
+                            (p == gs[i].npass - 1) == (last == 1) && descs[i][p].tile_rows == rows)
+                            L.d[L.nd++] = descs[i][p];
+                    if (L.nd == 0) continue;
+                    const int ti = p == 0 ? in_t : acc_t;
+                    hipError_t e = launch_pass(L, ti, acc_t, stream, op);
+                    if (e != hipSuccess) return hip_fail(e, "forward pass launch");
+                }
             }
         }
     }
@@ -471,6 +493,24 @@ int fht_engine_status(const void* workspace, void* stream)
     return FHT_OK;
 }
 
+int fht_set_tile_rows(int k, int rows)
+{
+    if (k < 3 || k > 16) return fail(FHT_ERR_INVALID, "k %d outside 3..16", k);
+    if (rows != 0 && rows != kTileRows && rows != kNarrowRows)
+        return fail(FHT_ERR_INVALID, "tile rows %d: 0 (default), %d or %d", rows, kNarrowRows, kTileRows);
+    std::lock_guard<std::mutex> lock(g_split_mu);
+    g_rows[k] = rows;
+    return FHT_OK;
+}
+
+int fht_tile_rows(int side, int* rows)
+{
+    if (!rows) return fail(FHT_ERR_INVALID, "null output");
+    if (side < 1 || pow2_ceil(side) > FHT_MAX_SIDE) return fail(FHT_ERR_INVALID, "bad side %d", side);
+    *rows = tile_rows_for(ilog2(pow2_ceil(side)), 5);
+    return FHT_OK;
+}
+
 int fht_set_pass_split(int k, int npass, const int* passes)
 {
     if (k < 3 || k > 16) return fail(FHT_ERR_INVALID, "k %d outside 3..16", k);
@@ -501,19 +541,38 @@ int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream)
     if (!dtype_pair_ok(in_t, acc_t)) return fail(FHT_ERR_INVALID, "unsupported dtype pair (%d, %d)", in_t, acc_t);
     if (reps < 1 || reps > 1000) return fail(FHT_ERR_INVALID, "reps %d outside 1..1000", reps);
     const int kh = ilog2(pow2_ceil(h)), kw = ilog2(pow2_ceil(w));
-    // the stage counts with more than one candidate split
+    // candidates per stage count: every split into the fewest passes, each
+    // with 64-row tiles and, when some pass has at most 5 stages, 32-row tiles
+    struct Cfg {
+        std::vector<int> split;
+        int rows;
+    };
+    auto candidates = [](int k) {
+        std::vector<Cfg> out;
+        for (auto& sp : split_candidates(k)) {
+            out.push_back({sp, kTileRows});
+            bool narrow_ok = false;
+            for (int g : sp) narrow_ok |= g <= 5;
+            if (narrow_ok) out.push_back({sp, kNarrowRows});
+        }
+        return out;
+    };
+    auto apply = [](int k, const Cfg& c) {
+        fht_set_pass_split(k, (int)c.split.size(), c.split.data());
+        fht_set_tile_rows(k, c.rows);
+    };
     std::vector<int> ks;
     for (int k : {kh, kw})
-        if (k >= 7 && split_candidates(k).size() > 1 && (ks.empty() || ks[0] != k)) ks.push_back(k);
+        if (k >= 3 && candidates(k).size() > 1 && (ks.empty() || ks[0] != k)) ks.push_back(k);
     if (ks.empty()) return FHT_OK;
-    std::vector<std::vector<int>> ca = split_candidates(ks[0]);
-    std::vector<std::vector<int>> cb = ks.size() > 1 ? split_candidates(ks[1]) : std::vector<std::vector<int>>{{}};
+    const std::vector<Cfg> ca = candidates(ks[0]);
+    const std::vector<Cfg> cb = ks.size() > 1 ? candidates(ks[1]) : std::vector<Cfg>{Cfg{{}, 0}};
     // buffers for the largest workspace over every combination
     size_t ws_max = 0;
     for (auto& a : ca)
         for (auto& b : cb) {
-            fht_set_pass_split(ks[0], (int)a.size(), a.data());
-            if (ks.size() > 1) fht_set_pass_split(ks[1], (int)b.size(), b.data());
+            apply(ks[0], a);
+            if (ks.size() > 1) apply(ks[1], b);
             size_t need = 0;
             fht_workspace_size(w, h, FHT_FULL, in_t, acc_t, &need);
             ws_max = need > ws_max ? need : ws_max;
@@ -531,12 +590,12 @@ int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream)
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = -1.f;
-    std::vector<int> best_a, best_b;
+    Cfg best_a, best_b;
     for (auto& a : ca) {
         for (auto& b : cb) {
             if (e != hipSuccess) break;
-            fht_set_pass_split(ks[0], (int)a.size(), a.data());
-            if (ks.size() > 1) fht_set_pass_split(ks[1], (int)b.size(), b.data());
+            apply(ks[0], a);
+            if (ks.size() > 1) apply(ks[1], b);
             rc = fht_forward(img, in_t, w, h, w, hough, acc_t, cols, FHT_FULL, 0, ws, ws_max > 256 ? ws_max : 256,
                              stream);  // warm-up
             if (rc) break;
@@ -562,13 +621,15 @@ int fht_autotune(int w, int h, int in_t, int acc_t, int reps, void* stream)
     hipFree(img);
     hipFree(hough);
     hipFree(ws);
-    // keep the fastest (or the default rule if timing failed)
-    fht_set_pass_split(ks[0], 0, nullptr);
-    if (ks.size() > 1) fht_set_pass_split(ks[1], 0, nullptr);
+    // keep the fastest (or the default rules if timing failed)
+    for (int k : ks) {
+        fht_set_pass_split(k, 0, nullptr);
+        fht_set_tile_rows(k, 0);
+    }
     if (e != hipSuccess) return hip_fail(e, "autotune");
     if (rc) return rc;
-    fht_set_pass_split(ks[0], (int)best_a.size(), best_a.data());
-    if (ks.size() > 1) fht_set_pass_split(ks[1], (int)best_b.size(), best_b.data());
+    apply(ks[0], best_a);
+    if (ks.size() > 1) apply(ks[1], best_b);
     return FHT_OK;
 }
 

@@ -4,7 +4,7 @@
 // engine group whose pointers are byte offsets: image index, offset in the
 // packed Hough buffer, offset in the workspace.  A call copies the template
 // into the workspace with the pointers resolved (one small kernel), then runs
-// one table-driven launch per (pass, depth, last-pass) class: every tile of
+// one table-driven launch per (pass, depth, last-pass, tile height) class: every tile of
 // every image of that class in one grid.  Images are processed in chunks
 // whose intermediate bands fit a fixed budget, so the workspace stays
 // bounded; chunks follow each other on the stream.  Everything enqueued is a
@@ -28,6 +28,7 @@ struct BatchLaunch {
     int n_groups;
     int n_items;
     int G;
+    int rows;         // tile height of the class (64 or 32)
     bool first, last;
 };
 
@@ -135,8 +136,8 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
             ++i1;
         }
         band_peak = std::max(band_peak, band);
-        // groups of this chunk, by (pass, depth, last)
-        struct Item { EngineGroup e; BatchTemplate r; int p, G, last; };
+        // groups of this chunk, by (pass, depth, last, tile height)
+        struct Item { EngineGroup e; BatchTemplate r; int p, G, last, rows; };
         std::vector<Item> items;
         for (int i = i0; i < i1; ++i) {
             for (int q = 0; q < nq; ++q) {
@@ -162,18 +163,21 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
                     it.p = p;
                     it.G = g.G[p];
                     it.last = p + 1 == g.npass;
+                    it.rows = it.e.d.tile_rows;
                     items.push_back(it);
                 }
             }
         }
         for (int p = 0; p < 4; ++p)
             for (int G = kMaxG; G >= 0; --G)
-                for (int last = 0; last < 2; ++last) {
+                for (int last = 0; last < 2; ++last)
+                for (int rows = kTileRows; rows >= kNarrowRows; rows /= 2) {
                     BatchLaunch L{};
                     L.first_group = (int)tmpl.size();
                     int64_t item = 0;
                     for (const Item& it : items) {
-                        if (it.p != p || it.G != G || it.last != last) continue;
+                        if (it.p != p || it.G != G || it.last != last || (G > 2 && it.rows != rows)) continue;
+                        if (G <= 2 && rows != kTileRows) continue;
                         EngineGroup e = it.e;
                         e.first_item = (int)item;
                         item += e.count;
@@ -188,6 +192,7 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
                     if (L.n_groups == 0) continue;
                     L.n_items = (int)item;
                     L.G = G;
+                    L.rows = rows;
                     L.first = p == 0;
                     L.last = last != 0;
                     P->launches.push_back(L);
@@ -242,7 +247,7 @@ int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* ho
         if (L.G <= 2)  // quadrants of at most 4 rows: one thread per Hough cell
             e = launch_table_direct(table + L.first_group, L.n_groups, L.n_items, ti, P->acc_t, s);
         else
-            e = launch_table(table + L.first_group, L.n_groups, L.n_items, L.G, L.first, L.last,
+            e = launch_table(table + L.first_group, L.n_groups, L.n_items, L.G, L.first, L.last, L.rows,
                              L.first ? ti : P->acc_t, P->acc_t, s);
         if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }

@@ -529,12 +529,12 @@ __device__ __forceinline__ void fwd_phase_b(T (&a)[8][8], T (&b)[8][8], T* lds, 
 // Stores of one forward tile: rows of b to the band of the pass, or (last
 // pass) to the Hough image with the merged-row mapping, the mirror and the
 // optional fhtshift roll.
-template <typename T, int GB, bool LAST>
+template <typename T, int GB, bool LAST, int NW>
 __device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, int wave, int lane, const T (&b)[8][8])
 {
     constexpr int G = 3 + GB;
     constexpr int VW = kWinCols - (1 << G);
-    constexpr int NMINI = 1 << (6 - G);
+    constexpr int NMINI = (NW * 8) >> G;
     const int j0 = d.j0;
     const int n_mini = d.n >> G;
     const int wc0 = 8 * lane;
@@ -589,14 +589,17 @@ __device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, in
 }
 
 
-// One tile (64 rows x 512 columns) of one forward pass of G = 3 + GB stages.
-// rt: row tile, win: column window.  Every thread of the workgroup calls it.
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP = 0>
+// One tile (NW * 8 rows x 512 columns: NW waves of 8 rows) of one forward
+// pass of G = 3 + GB stages.  rt: row tile, win: column window.  Every thread
+// of the workgroup calls it; lds holds NW * 4 rows of kLdsRow words.
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP = 0, int NW = 8>
 __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* lds)
 {
     constexpr int G = 3 + GB;
+    constexpr int ROWS = NW * 8;
+    static_assert(ROWS >= (1 << G), "a tile holds whole mini-transforms");
     constexpr int VW = kWinCols - (1 << G);      // stored columns per tile
-    constexpr int NMINI = 1 << (6 - G);          // mini-transforms of 2^G rows per tile
+    constexpr int NMINI = ROWS >> G;             // mini-transforms of 2^G rows per tile
     const int lane = threadIdx.x & 63;
     const int wave = uniform(threadIdx.x >> 6);
     const int j0 = d.j0;
@@ -608,7 +611,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
     // (section 3.2, case c) is written as zeros without loading anything.
     bool black = false;
     if (LAST && d.black_ok) {
-        const int s_max = min(rt * 64 + 63, d.n - 1);
+        const int s_max = min(rt * ROWS + ROWS - 1, d.n - 1);
         black = xi0 >= d.black_lo && xi0 + VW <= d.black_lo + d.n - s_max;
     }
 
@@ -714,7 +717,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         fwd_phase_b<T, GB, OP>(a, b, lds, wave, lane);
     }
 
-    fwd_store<T, GB, LAST>(d, rt, xi0, wave, lane, b);
+    fwd_store<T, GB, LAST, NW>(d, rt, xi0, wave, lane, b);
 }
 
 // Tile order.  Workgroups are dispatched to the 8 XCDs round-robin by block
@@ -729,10 +732,12 @@ __device__ __forceinline__ int xcd_tile(int block, int n_tiles)
     return (block % kXcds) * per + block / kXcds;
 }
 
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP>
-__global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch L)
+// NW = 8: 64-row tiles, two workgroups per CU; NW = 4: 32-row tiles (passes
+// of at most 5 stages), half the LDS, four workgroups per CU.
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP, int NW>
+__global__ __launch_bounds__(NW * 64, 4) void fht_pass_kernel(const PassLaunch L)
 {
-    __shared__ T lds[kTileRows / 2 * kLdsRow];
+    __shared__ T lds[NW * 4 * kLdsRow];
     int t = xcd_tile(blockIdx.x, L.n_tiles);
     if (t >= L.n_tiles) return;
     int z = 0;
@@ -744,16 +749,16 @@ __global__ __launch_bounds__(kThreads, 4) void fht_pass_kernel(const PassLaunch 
     // dynamic index had every stored row read its fields again
     const PassDesc d = L.d[z];
     const int rt = t / d.n_windows;
-    fwd_tile<TIn, T, GB, FIRST, LAST, OP>(d, rt, t - rt * d.n_windows, lds);
+    fwd_tile<TIn, T, GB, FIRST, LAST, OP, NW>(d, rt, t - rt * d.n_windows, lds);
 }
 
 // Many passes (of many images) of one kind in one launch: block -> item ->
 // group through the groups' first_item prefix, as in the engine queue.
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kThreads, 4) void fht_table_kernel(const EngineGroup* __restrict__ table, int n_groups,
-                                                                 int n_items)
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int NW>
+__global__ __launch_bounds__(NW * 64, 4) void fht_table_kernel(const EngineGroup* __restrict__ table, int n_groups,
+                                                                int n_items)
 {
-    __shared__ T lds[kTileRows / 2 * kLdsRow];
+    __shared__ T lds[NW * 4 * kLdsRow];
     const int item = xcd_tile(blockIdx.x, n_items);
     if (item >= n_items) return;
     int lo = 0, hi = n_groups - 1;
@@ -767,7 +772,7 @@ __global__ __launch_bounds__(kThreads, 4) void fht_table_kernel(const EngineGrou
     const PassDesc d = table[uniform(lo)].d;
     const int local = item - table[uniform(lo)].first_item;
     const int rt = local / d.n_windows;
-    fwd_tile<TIn, T, GB, FIRST, LAST>(d, rt, local - rt * d.n_windows, lds);
+    fwd_tile<TIn, T, GB, FIRST, LAST, 0, NW>(d, rt, local - rt * d.n_windows, lds);
 }
 
 // ------------------------------------------------- persistent forward engine

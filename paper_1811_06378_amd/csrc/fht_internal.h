@@ -13,6 +13,7 @@ namespace fht {
 // Tile geometry of the fused pass kernel.  One workgroup holds 64 rows x 512
 // columns: 8 waves, each lane owns 8 consecutive columns of 8 rows.
 constexpr int kTileRows = 64;
+constexpr int kNarrowRows = 32;         // narrow tiles: 4 waves, passes of at most 5 stages
 constexpr int kLaneCols = 8;
 constexpr int kWinCols = 512;           // columns loaded per tile
 constexpr int kThreads = 512;
@@ -58,6 +59,7 @@ struct PassDesc {
     int black_ok;         // 1: tiles wholly inside that zone are written as zeros without loads
     int scale_num, scale_den;  // first pass: source sample floor(x * den / num) along the
                                // sheared axis (section 4 scale); 0 = no scaling
+    int tile_rows;        // 64 (8 waves) or 32 (4 waves, G <= 5); n_row_tiles = ceil(n / tile_rows)
 };
 
 constexpr int kMaxDescs = 4;
@@ -127,8 +129,8 @@ hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s, 
 hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s, int op = 0);
 hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc_t, hipStream_t s);
 // table: device array of n_groups groups of one kind (same G, first/last)
-hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int in_t,
-                        int acc_t, hipStream_t s);
+hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int rows,
+                        int in_t, int acc_t, hipStream_t s);
 // direct quadrants (n <= 4) of a batch: n x W cells per group
 hipError_t launch_table_direct(const EngineGroup* table, int n_groups, int n_items, int in_t, int acc_t,
                                hipStream_t s);
@@ -147,7 +149,8 @@ int engine_grid_size();
 // instantiation (in_t < 0: adjoint kernels, one type; op >= 0: the forward
 // pass kernel's trailing operation argument), and the event pair
 // around one launch.  timing_begin returns -1 when timing is off.
-std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last, int op = -1);
+std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last, int op = -1,
+                        int nw = -1);
 bool timing_on();
 int timing_begin(const std::string& name, hipStream_t s);
 void timing_end(int slot, hipStream_t s);

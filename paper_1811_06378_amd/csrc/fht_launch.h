@@ -7,7 +7,7 @@
 
 namespace fht {
 
-template <typename TIn, typename T, int GB, int OP>
+template <typename TIn, typename T, int GB, int OP, int NW>
 hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
 {
     PassLaunch L = L0;
@@ -15,23 +15,25 @@ hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
     for (int i = 0; i < L.nd; ++i) L.n_tiles += L.d[i].n_row_tiles * L.d[i].n_windows;
     if (L.n_tiles == 0) return hipSuccess;
     const bool first = L.d[0].src_kind != SRC_BAND, last = L.d[0].dst_kind == DST_HOUGH;
-    const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds);
-    if (first && last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP>), grid, dim3(kThreads), 0, s, L);
-    else if (first) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP>), grid, dim3(kThreads), 0, s, L);
-    else if (last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true, OP>), grid, dim3(kThreads), 0, s, L);
-    else hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false, OP>), grid, dim3(kThreads), 0, s, L);
+    const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds), block(NW * 64);
+    if (first && last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP, NW>), grid, block, 0, s, L);
+    else if (first) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP, NW>), grid, block, 0, s, L);
+    else if (last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true, OP, NW>), grid, block, 0, s, L);
+    else hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false, OP, NW>), grid, block, 0, s, L);
     return hipGetLastError();
 }
 
-// all descriptors of one launch share G and first/last
+// all descriptors of one launch share G, first/last and the tile height;
+// 32-row tiles exist for passes of at most 5 stages
 template <typename TIn, typename T, int OP = 0>
 hipError_t launch_pass_t(const PassLaunch& L, hipStream_t s)
 {
+    const bool narrow = L.d[0].tile_rows == kNarrowRows;
     switch (L.d[0].G) {
-    case 3: return launch_pass_g<TIn, T, 0, OP>(L, s);
-    case 4: return launch_pass_g<TIn, T, 1, OP>(L, s);
-    case 5: return launch_pass_g<TIn, T, 2, OP>(L, s);
-    case 6: return launch_pass_g<TIn, T, 3, OP>(L, s);
+    case 3: return narrow ? launch_pass_g<TIn, T, 0, OP, 4>(L, s) : launch_pass_g<TIn, T, 0, OP, 8>(L, s);
+    case 4: return narrow ? launch_pass_g<TIn, T, 1, OP, 4>(L, s) : launch_pass_g<TIn, T, 1, OP, 8>(L, s);
+    case 5: return narrow ? launch_pass_g<TIn, T, 2, OP, 4>(L, s) : launch_pass_g<TIn, T, 2, OP, 8>(L, s);
+    case 6: return narrow ? hipErrorInvalidValue : launch_pass_g<TIn, T, 3, OP, 8>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -44,30 +46,38 @@ hipError_t launch_engine_g(const EngineArgs& A, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename TIn, typename T, int GB>
+template <typename TIn, typename T, int GB, int NW>
 hipError_t launch_table_g(const EngineGroup* table, int n_groups, int n_items, bool first, bool last, hipStream_t s)
 {
-    const dim3 grid((n_items + kXcds - 1) / kXcds * kXcds);
+    const dim3 grid((n_items + kXcds - 1) / kXcds * kXcds), block(NW * 64);
     if (first && last)
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, true>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, true, NW>), grid, block, 0, s, table, n_groups, n_items);
     else if (first)
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, false>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, false, NW>), grid, block, 0, s, table, n_groups, n_items);
     else if (last)
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, true>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, true, NW>), grid, block, 0, s, table, n_groups, n_items);
     else
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, false>), grid, dim3(kThreads), 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, false, NW>), grid, block, 0, s, table, n_groups,
+                           n_items);
     return hipGetLastError();
 }
 
 template <typename TIn, typename T>
-hipError_t launch_table_t(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last,
+hipError_t launch_table_t(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int rows,
                           hipStream_t s)
 {
+    const bool narrow = rows == kNarrowRows;
     switch (G) {
-    case 3: return launch_table_g<TIn, T, 0>(table, n_groups, n_items, first, last, s);
-    case 4: return launch_table_g<TIn, T, 1>(table, n_groups, n_items, first, last, s);
-    case 5: return launch_table_g<TIn, T, 2>(table, n_groups, n_items, first, last, s);
-    case 6: return launch_table_g<TIn, T, 3>(table, n_groups, n_items, first, last, s);
+    case 3:
+        return narrow ? launch_table_g<TIn, T, 0, 4>(table, n_groups, n_items, first, last, s)
+                      : launch_table_g<TIn, T, 0, 8>(table, n_groups, n_items, first, last, s);
+    case 4:
+        return narrow ? launch_table_g<TIn, T, 1, 4>(table, n_groups, n_items, first, last, s)
+                      : launch_table_g<TIn, T, 1, 8>(table, n_groups, n_items, first, last, s);
+    case 5:
+        return narrow ? launch_table_g<TIn, T, 2, 4>(table, n_groups, n_items, first, last, s)
+                      : launch_table_g<TIn, T, 2, 8>(table, n_groups, n_items, first, last, s);
+    case 6: return narrow ? hipErrorInvalidValue : launch_table_g<TIn, T, 3, 8>(table, n_groups, n_items, first, last, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -169,7 +179,7 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
     hipError_t launch_engine_##name(const EngineArgs& A, int G, int grid, hipStream_t s); \
     hipError_t launch_direct_##name(const PassLaunch& L, int k, hipStream_t s);                 \
     hipError_t launch_table_##name(const EngineGroup* table, int n_groups, int n_items, int G, bool first, \
-                                   bool last, hipStream_t s);                                            \
+                                   bool last, int rows, hipStream_t s);                                  \
     hipError_t launch_table_direct_##name(const EngineGroup* table, int n_groups, int n_items, hipStream_t s);
 FHT_DECLARE_FWD(u8)
 FHT_DECLARE_FWD(i32)

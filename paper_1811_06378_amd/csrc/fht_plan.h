@@ -35,6 +35,7 @@ int hip_fail(hipError_t e, const char* what);
 int64_t pow2_ceil(int64_t v);
 int ilog2(int64_t p);
 void pass_split(int k, int* npass, int* G);
+int tile_rows_for(int k, int G);
 QuadGeom quad_geom(int w, int h, int q, int S1);
 size_t quad_band_bytes(const QuadGeom& g, int p, int elem);
 size_t layout_bands(QuadGeom* gs, int nq, int elem, size_t base);

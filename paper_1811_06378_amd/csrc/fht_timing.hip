@@ -57,11 +57,13 @@ int class_of(const std::string& name)
 
 }  // namespace
 
-std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last, int op)
+std::string kernel_name(const char* kernel, int in_t, int acc_t, int GB, bool first, bool last, int op, int nw)
 {
     char buf[160];
-    char tail[16] = "";
-    if (op >= 0) snprintf(tail, sizeof tail, ", %d", op);
+    char tail[32] = "";
+    if (op >= 0 && nw >= 0) snprintf(tail, sizeof tail, ", %d, %d", op, nw);
+    else if (op >= 0) snprintf(tail, sizeof tail, ", %d", op);
+    else if (nw >= 0) snprintf(tail, sizeof tail, ", %d", nw);
     if (in_t < 0)
         snprintf(buf, sizeof buf, "fht::%s<%s, %d, %s, %s%s>", kernel, type_name(acc_t), GB, first ? "true" : "false",
                  last ? "true" : "false", tail);

@@ -77,6 +77,8 @@ SIGNATURES = {
     "fht_cell_segment": (_I, [_I, _I, _U, _I64, _I64, _I, _PI32]),
     "fht_peaks": (_I, [_P, _I, _I64, _I64, _I64, _I, ctypes.c_double, _P, _I, _P, _P]),
     "fht_engine_status": (_I, [_P, _P]),
+    "fht_set_tile_rows": (_I, [_I, _I]),
+    "fht_tile_rows": (_I, [_I, ctypes.POINTER(_I)]),
     "fht_set_pass_split": (_I, [_I, _I, ctypes.POINTER(_I)]),
     "fht_autotune": (_I, [_I, _I, _I, _I, _I, _P]),
     "fht_timing_enable": (_I, [_I]),
@@ -215,6 +217,20 @@ def set_pass_split(k: int, passes=None):
         return
     arr = (ctypes.c_int * len(passes))(*passes)
     _check(lib().fht_set_pass_split(k, len(passes), arr), "fht_set_pass_split")
+
+
+def set_tile_rows(k: int, rows: int | None = None):
+    """Tile height (32 or 64) for passes of at most 5 stages of quadrants
+    with 2^k rows (None restores the default rule).  Cached stack plans are
+    dropped."""
+    _plan_cache.clear()
+    _check(lib().fht_set_tile_rows(k, 0 if rows is None else int(rows)), "fht_set_tile_rows")
+
+
+def tile_rows(side: int) -> int:
+    r = ctypes.c_int()
+    _check(lib().fht_tile_rows(side, ctypes.byref(r)), "fht_tile_rows")
+    return r.value
 
 
 def autotune(w: int, h: int, in_dtype=torch.float32, reps: int = 20):

@@ -274,3 +274,21 @@ def test_binding_rejects_misshaped_tensors_before_any_launch():
         fht.forward(img, out=torch.zeros((rows, cols)))
     with pytest.raises(ValueError, match="device tensor|256-byte aligned"):
         fht.adjoint(G, w, h, out=torch.zeros((h, w)))
+
+
+def test_tile_rows_setting_and_validation():
+    """The tile height of passes of at most 5 stages: 32 by default, settable
+    per stage count, validated before any HIP call."""
+    assert fht.tile_rows(1024) == 32
+    fht.set_tile_rows(10, 64)
+    try:
+        assert fht.tile_rows(1024) == 64
+        assert fht.tile_rows(512) == 32
+    finally:
+        fht.set_tile_rows(10, None)
+    assert fht.tile_rows(1024) == 32
+    for k, rows in [(2, 32), (17, 32), (10, 48), (10, 16)]:
+        with pytest.raises(ValueError):
+            fht.set_tile_rows(k, rows)
+    with pytest.raises(ValueError):
+        fht.tile_rows(0)
