@@ -411,7 +411,11 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
         hipError_t e = launch_direct(L, gs[i].k, in_t, acc_t, stream, op);
         if (e != hipSuccess) return hip_fail(e, "direct launch");
     }
-    if (use_engine() && op == 0) {
+    bool sheared = false;
+    for (int i = 0; i < nq; ++i) sheared |= descs[i][0].S1 != 0 || descs[i][0].scale_num != 0;
+    // the engine runs unsheared, unscaled sources only; the angle range
+    // always takes the per-pass launches
+    if (use_engine() && op == 0 && !sheared) {
         std::vector<EngineGroup> groups;
         const int total = append_engine_groups(gs, descs, nq, groups, 0);
         return run_engine(groups, nullptr, total, sync, in_t, acc_t, stream);

@@ -437,6 +437,19 @@ __device__ __forceinline__ void patch_image_row(const PassDesc& d, int R, int e0
     }
 }
 
+// Element loads of unsheared, unscaled image row R at the run starting at
+// column e0 (boundary lanes of the first pass).
+template <typename TIn, typename T>
+__device__ __forceinline__ void patch_image_row_plain(const PassDesc& d, int R, int e0, T (&v)[8])
+{
+    const TIn* row = reinterpret_cast<const TIn*>(d.src) + (long long)R * d.src_ld;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int e = run_col(e0, c, d.W, d.mirror);
+        v[c] = (R < d.img_h && e < d.img_w) ? to_acc<T>(row[e]) : (T)0;
+    }
+}
+
 // Element-load rows (transposed image with a shear, or a scaled source):
 // zeros now, every element loaded by patch_image_row.
 template <typename TIn, typename T>
@@ -592,7 +605,12 @@ __device__ __forceinline__ void fwd_store(const PassDesc& d, int rt, int xi0, in
 // One tile (NW * 8 rows x 512 columns: NW waves of 8 rows) of one forward
 // pass of G = 3 + GB stages.  rt: row tile, win: column window.  Every thread
 // of the workgroup calls it; lds holds NW * 4 rows of kLdsRow words.
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP = 0, int NW = 8>
+// SRCM, the first pass's image sources: 0 unsheared rows or the transposed
+// image; 1 rows sheared for the angle range; 2 element loads (scaled sources,
+// sheared transposed sources).  Each kernel holds only its own source path:
+// the element path alone is about 80 KB of code, and with every path in one
+// kernel the instruction fetches delayed every tile of small transforms.
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP = 0, int NW = 8, int SRCM = 0>
 __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* lds)
 {
     constexpr int G = 3 + GB;
@@ -636,9 +654,39 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
         if (!active) {
 #pragma unroll
             for (int r = 0; r < 8; ++r) zero8(a[r]);
-        } else if (FIRST && d.src_kind == SRC_IMAGE_T && d.S1 == 0 && d.scale_num == 0) {
-            // first pass (u = 0): the wave's rows are 8 consecutive image columns
-            load_rows_transposed<TIn, T>(d, (B << G) + (tr0 & ((1 << G) - 1)), xi0, lane, a);
+        } else if constexpr (FIRST && SRCM == 0) {
+            if (d.src_kind == SRC_IMAGE_T) {
+                // the wave's rows are 8 consecutive image columns (u = 0)
+                load_rows_transposed<TIn, T>(d, (B << G) + (tr0 & ((1 << G) - 1)), xi0, lane, a);
+            } else {
+                // the wave's 8 rows are consecutive image rows read at the
+                // same columns, so the lane's column run is computed once;
+                // every row's loads are issued before the first wait
+                const int R0 = (B << G) + (tr0 & ((1 << G) - 1));
+                const int ec = lane_run_start(xi0, 0, lane, d.W, d.mirror);
+                const bool col_fast = ec + 8 <= d.img_w;
+                const bool col_zero = ec >= d.img_w && ec + 8 <= d.W;
+                const TIn* p = reinterpret_cast<const TIn*>(d.src) + (long long)R0 * d.src_ld + ec;
+                bool patch[8];
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const bool row_ok = R0 + r < d.img_h;
+                    const bool fast = row_ok && col_fast;
+                    load8_src<TIn, T>(fast ? p + (long long)r * d.src_ld : zero_page<TIn>(), a[r]);
+                    patch[r] = row_ok && !col_fast && !col_zero;
+                    any |= patch[r];
+                }
+                if (d.mirror) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) reverse8(a[r]);
+                }
+                if (__any(any)) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if (patch[r]) patch_image_row_plain<TIn, T>(d, R0 + r, ec, a[r]);
+                }
+            }
         } else {
             int e0[8];
             bool patch[8];
@@ -647,30 +695,7 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
             // The source kind is chosen once for all rows: a choice per row
             // ends every row in a merge of two paths, where the register
             // moves wait for that row's loads before the next row's issue.
-            const bool vector_rows = !FIRST || (d.src_kind == SRC_IMAGE && d.scale_num == 0);
-            if (FIRST && vector_rows && d.S1 == 0) {
-                // first pass without a shear: the wave's 8 rows are consecutive
-                // image rows read at the same columns, so the lane's column
-                // run is computed once
-                const int R0 = (B << G) + (tr0 & ((1 << G) - 1));
-                const int ec = lane_run_start(xi0, 0, lane, d.W, d.mirror);
-                const bool col_fast = ec + 8 <= d.img_w;
-                const bool col_zero = ec >= d.img_w && ec + 8 <= d.W;
-                const TIn* p = reinterpret_cast<const TIn*>(d.src) + (long long)R0 * d.src_ld + ec;
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const bool row_ok = R0 + r < d.img_h;
-                    const bool fast = row_ok && col_fast;
-                    load8_src<TIn, T>(fast ? p + (long long)r * d.src_ld : zero_page<TIn>(), a[r]);
-                    e0[r] = ec;
-                    patch[r] = row_ok && !col_fast && !col_zero;
-                    any |= patch[r];
-                }
-                if (d.mirror) {
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) reverse8(a[r]);
-                }
-            } else if (vector_rows) {
+            if constexpr (!FIRST || SRCM == 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int m = (tr0 + r) & ((1 << G) - 1);
@@ -702,7 +727,8 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& d, int rt, int win, T* 
                     if (patch[r]) {
                         const int m = (tr0 + r) & ((1 << G) - 1);
                         const int R = (B << (j0 + G)) + (m << j0) + u;
-                        if constexpr (FIRST) patch_image_row<TIn, T>(d, R, e0[r], a[r]);
+                        if constexpr (FIRST && SRCM == 1) patch_image_row_plain<TIn, T>(d, R, e0[r], a[r]);
+                        else if constexpr (FIRST) patch_image_row<TIn, T>(d, R, e0[r], a[r]);
                         else patch_band_row<T>(band + (long long)band_row(R, j0, k) * d.src_ld, d.src_bw, d.W, e0[r],
                                                a[r]);
                     }
@@ -734,7 +760,7 @@ __device__ __forceinline__ int xcd_tile(int block, int n_tiles)
 
 // NW = 8: 64-row tiles, two workgroups per CU; NW = 4: 32-row tiles (passes
 // of at most 5 stages), half the LDS, four workgroups per CU.
-template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP, int NW>
+template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int OP, int NW, int SRCM>
 __global__ __launch_bounds__(NW * 64, 4) void fht_pass_kernel(const PassLaunch L)
 {
     __shared__ T lds[NW * 4 * kLdsRow];
@@ -749,7 +775,7 @@ __global__ __launch_bounds__(NW * 64, 4) void fht_pass_kernel(const PassLaunch L
     // dynamic index had every stored row read its fields again
     const PassDesc d = L.d[z];
     const int rt = t / d.n_windows;
-    fwd_tile<TIn, T, GB, FIRST, LAST, OP, NW>(d, rt, t - rt * d.n_windows, lds);
+    fwd_tile<TIn, T, GB, FIRST, LAST, OP, NW, SRCM>(d, rt, t - rt * d.n_windows, lds);
 }
 
 // Many passes (of many images) of one kind in one launch: block -> item ->

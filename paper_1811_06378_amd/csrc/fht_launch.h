@@ -16,10 +16,38 @@ hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
     if (L.n_tiles == 0) return hipSuccess;
     const bool first = L.d[0].src_kind != SRC_BAND, last = L.d[0].dst_kind == DST_HOUGH;
     const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds), block(NW * 64);
-    if (first && last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP, NW>), grid, block, 0, s, L);
-    else if (first) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP, NW>), grid, block, 0, s, L);
-    else if (last) hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true, OP, NW>), grid, block, 0, s, L);
-    else hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false, OP, NW>), grid, block, 0, s, L);
+    // first passes of sheared or scaled sources (angle range, sum only) take
+    // the kernel with their source path; every descriptor of a launch agrees
+    int mode = 0;
+    for (int i = 0; i < L.nd; ++i) {
+        const PassDesc& d = L.d[i];
+        const int m = !first ? 0 : d.scale_num != 0 ? 2 : d.S1 == 0 ? 0 : d.src_kind == SRC_IMAGE ? 1 : 2;
+        if (i > 0 && m != mode) return hipErrorInvalidValue;
+        mode = m;
+    }
+    if (mode != 0) {
+        if constexpr (OP == 0) {
+            if (mode == 1 && last)
+                hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP, NW, 1>), grid, block, 0, s, L);
+            else if (mode == 1)
+                hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP, NW, 1>), grid, block, 0, s, L);
+            else if (last)
+                hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP, NW, 2>), grid, block, 0, s, L);
+            else
+                hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP, NW, 2>), grid, block, 0, s, L);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    if (first && last)
+        hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, true, OP, NW, 0>), grid, block, 0, s, L);
+    else if (first)
+        hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, true, false, OP, NW, 0>), grid, block, 0, s, L);
+    else if (last)
+        hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, true, OP, NW, 0>), grid, block, 0, s, L);
+    else
+        hipLaunchKernelGGL((fht_pass_kernel<TIn, T, GB, false, false, OP, NW, 0>), grid, block, 0, s, L);
     return hipGetLastError();
 }
 
