@@ -950,10 +950,10 @@ __device__ __forceinline__ void adj_patch_hough(const AdjDesc& d, int s_row, int
 // contribution first, then the other quadrants' partial images in quadrant
 // order (pi: the element's index in the partial images).  Every partial is
 // loaded before the first add, so the loads of a row go out together.
-template <typename T>
+template <typename T, bool ACC>
 __device__ __forceinline__ void acc_store8(const AdjDesc& d, T* p, int64_t pi, const T (&v)[8])
 {
-    if (!d.accumulate) {
+    if constexpr (!ACC) {
         store8<T>(p, v);
         return;
     }
@@ -973,10 +973,10 @@ __device__ __forceinline__ void acc_store8(const AdjDesc& d, T* p, int64_t pi, c
     store8<T>(p, o);
 }
 
-template <typename T>
+template <typename T, bool ACC>
 __device__ __forceinline__ T acc_value(const AdjDesc& d, int64_t pi, T v)
 {
-    if (!d.accumulate) return v;
+    if constexpr (!ACC) return v;
     // fixed indices: a loop over part[k] would index the descriptor
     // dynamically and move it to scratch memory
     T o = v + reinterpret_cast<const T*>(d.part[0])[pi];
@@ -1023,7 +1023,10 @@ __device__ __forceinline__ void adj_exchange(T (&b)[8][8], T (&a)[8][8], T* lds,
     }
 }
 
-template <typename T, int GB, bool FIRST, bool LAST>
+// ACC: the image pass that adds the other quadrants' partial images (the
+// descriptors' accumulate flag); a separate instantiation keeps that code
+// out of every other adjoint kernel.
+template <typename T, int GB, bool FIRST, bool LAST, bool ACC = false>
 __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* lds)
 {
     constexpr int G = 3 + GB;
@@ -1152,13 +1155,13 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
                 T v[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) v[c] = d.mirror ? a[r][7 - c] : a[r][c];
-                acc_store8<T>(d, p + e0, (int64_t)R * d.part_ld + e0, v);
+                acc_store8<T, ACC>(d, p + e0, (int64_t)R * d.part_ld + e0, v);
             } else {
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int e = run_col(e0, c, W, d.mirror);
                     if (rel + c < cols && e < cols)
-                        p[e] = acc_value<T>(d, (int64_t)R * d.part_ld + e, a[r][c]);
+                        p[e] = acc_value<T, ACC>(d, (int64_t)R * d.part_ld + e, a[r][c]);
                 }
             }
         }
@@ -1176,23 +1179,23 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
             for (int r = 0; r < 8; ++r) v[r] = a[r][c];
             const int64_t pi = (int64_t)e * d.part_ld + R0;
             if (all_cols) {
-                acc_store8<T>(d, p, pi, v);
+                acc_store8<T, ACC>(d, p, pi, v);
             } else {
 #pragma unroll
                 for (int r = 0; r < 8; ++r)
-                    if (R0 + r < d.img_w) p[r] = acc_value<T>(d, pi + r, v[r]);
+                    if (R0 + r < d.img_w) p[r] = acc_value<T, ACC>(d, pi + r, v[r]);
             }
         }
     }
 }
 
-template <typename T, int GB, bool FIRST, bool LAST>
+template <typename T, int GB, bool FIRST, bool LAST, bool ACC>
 __global__ __launch_bounds__(kThreads, 4) void fht_adj_pass_kernel(const AdjLaunch L)
 {
     __shared__ T lds[kTileRows / 2 * kLdsRow];
     const AdjDesc d = L.d[blockIdx.z];  // a private copy: its fields stay in registers across the stores
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
-    adj_tile<T, GB, FIRST, LAST>(d, blockIdx.y, blockIdx.x, lds);
+    adj_tile<T, GB, FIRST, LAST, ACC>(d, blockIdx.y, blockIdx.x, lds);
 }
 
 // -------------------------------------------- direct form for n <= 4 rows
@@ -1307,7 +1310,7 @@ __global__ __launch_bounds__(256) void fht_adj_direct_kernel(const AdjLaunch L)
     T* p = d.dst_kind == 2 ? reinterpret_cast<T*>(d.dst) + (long long)x * d.dst_ld + R
                            : reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x;
     const int64_t pi = d.dst_kind == 2 ? (int64_t)x * d.part_ld + R : (int64_t)R * d.part_ld + x;
-    *p = acc_value<T>(d, pi, v);
+    *p = d.accumulate ? acc_value<T, true>(d, pi, v) : v;
 }
 
 // ------------------------------------------------ angle-range adjoint tail

@@ -160,10 +160,23 @@ hipError_t launch_adj_pass_g(const AdjLaunch& L, hipStream_t s)
     }
     const bool first = L.d[0].src_kind == 0, last = L.d[0].dst_kind != 0;
     const dim3 grid(wx, ry, L.nd);
-    if (first && last) hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, true>), grid, dim3(kThreads), 0, s, L);
-    else if (first) hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, false>), grid, dim3(kThreads), 0, s, L);
-    else if (last) hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, true>), grid, dim3(kThreads), 0, s, L);
-    else hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, false>), grid, dim3(kThreads), 0, s, L);
+    // image passes that add partial images run their own instantiation; all
+    // descriptors of a launch agree
+    const bool acc = last && L.d[0].accumulate != 0;
+    for (int i = 1; i < L.nd; ++i)
+        if ((last && L.d[i].accumulate != 0) != acc) return hipErrorInvalidValue;
+    if (first && last && acc)
+        hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, true, true>), grid, dim3(kThreads), 0, s, L);
+    else if (first && last)
+        hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, true, false>), grid, dim3(kThreads), 0, s, L);
+    else if (first)
+        hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, true, false, false>), grid, dim3(kThreads), 0, s, L);
+    else if (last && acc)
+        hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, true, true>), grid, dim3(kThreads), 0, s, L);
+    else if (last)
+        hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, true, false>), grid, dim3(kThreads), 0, s, L);
+    else
+        hipLaunchKernelGGL((fht_adj_pass_kernel<T, GB, false, false, false>), grid, dim3(kThreads), 0, s, L);
     return hipGetLastError();
 }
 

@@ -98,9 +98,13 @@ hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStr
 hipError_t launch_adjoint_pass(const AdjLaunch& L, int t, hipStream_t s)
 {
     int slot = -1;
-    if (timing_on())
-        slot = timing_begin(kernel_name("fht_adj_pass_kernel", -1, t, L.d[0].G - 3, L.d[0].src_kind == 0,
-                                        L.d[0].dst_kind != 0), s);
+    if (timing_on()) {
+        // the kernel's template arguments: type, GB, first, last, accumulate
+        std::string name = kernel_name("fht_adj_pass_kernel", -1, t, L.d[0].G - 3, L.d[0].src_kind == 0,
+                                       L.d[0].dst_kind != 0);
+        name.insert(name.size() - 1, (L.d[0].dst_kind != 0 && L.d[0].accumulate) ? ", true" : ", false");
+        slot = timing_begin(name, s);
+    }
     hipError_t e = hipErrorInvalidValue;
     if (t == 1) e = launch_adj_pass_i32(L, s);
     if (t == 2) e = launch_adj_pass_f32(L, s);
