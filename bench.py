@@ -384,7 +384,7 @@ def main():
     name = dominant
     launches, total_ms = kernels[name]
     avg_ms = total_ms / launches
-    alg = compulsory if "fht_pass_kernel<float, float, 3, false, true, 0, 8>" in name else None
+    alg = compulsory if "fht_pass_kernel<float, float, 3, false, true, 0, 8, 0>" in name else None
     pass_bytes = last_pass_algorithmic_bytes(fht, side, side, 4) if alg else None
     achieved = alg / (avg_ms * 1e-3) / 1e9 if alg else None
     traffic = committed_traffic(name)

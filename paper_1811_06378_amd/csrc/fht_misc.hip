@@ -35,9 +35,17 @@ static hipError_t launch_pass_typed(const PassLaunch& L, int in_t, int acc_t, in
 hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s, int op)
 {
     int slot = -1;
-    if (timing_on())
-        slot = timing_begin(kernel_name("fht_pass_kernel", in_t, acc_t, L.d[0].G - 3, L.d[0].src_kind != SRC_BAND,
-                                        L.d[0].dst_kind == DST_HOUGH, op, L.d[0].tile_rows / 8), s);
+    if (timing_on()) {
+        // template arguments as the kernel has them: ..., op, waves per tile,
+        // first-pass source mode (0 plain, 1 sheared rows, 2 element loads)
+        const PassDesc& d = L.d[0];
+        const bool first = d.src_kind != SRC_BAND;
+        const int mode = !first ? 0 : d.scale_num != 0 ? 2 : d.S1 == 0 ? 0 : d.src_kind == SRC_IMAGE ? 1 : 2;
+        std::string name = kernel_name("fht_pass_kernel", in_t, acc_t, d.G - 3, first, d.dst_kind == DST_HOUGH, op,
+                                       d.tile_rows / 8);
+        name.insert(name.size() - 1, ", " + std::to_string(mode));
+        slot = timing_begin(name, s);
+    }
     const hipError_t e = launch_pass_typed(L, in_t, acc_t, op, s);
     timing_end(slot, s);
     return e;

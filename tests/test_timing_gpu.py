@@ -27,8 +27,8 @@ def test_forward_launches_are_counted_per_kernel():
         fht.timing_enable(False)
     rep = fht.timing_report()
     # 1024: two passes of 5 stages (GB = 2), first pass from the image, last to the Hough image
-    first = "fht::fht_pass_kernel<float, float, 2, true, false, 0, %d>" % (fht.tile_rows(1024) // 8)
-    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0, %d>" % (fht.tile_rows(1024) // 8)
+    first = "fht::fht_pass_kernel<float, float, 2, true, false, 0, %d, 0>" % (fht.tile_rows(1024) // 8)
+    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0, %d, 0>" % (fht.tile_rows(1024) // 8)
     assert set(rep) == {first, last}, rep
     for name in (first, last):
         launches, total_ms = rep[name]
@@ -89,7 +89,7 @@ def test_nothing_recorded_under_graph_capture():
 
 def test_filter_records_only_matching_kernels():
     img = torch.from_numpy(synth.random_image(1024, 1024, "f32", seed=4)).cuda()
-    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0, %d>" % (fht.tile_rows(1024) // 8)
+    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0, %d, 0>" % (fht.tile_rows(1024) // 8)
     fht.timing_filter("2, false, true, 0, ")
     fht.timing_enable(True)
     try:
