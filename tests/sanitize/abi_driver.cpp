@@ -56,6 +56,14 @@ int main()
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_Q1, FHT_FLAG_SHIFTED, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_FULL, 0, p, 16, nullptr) == FHT_ERR_WORKSPACE);
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_FULL, 0, (char*)p + 4, 1u << 30, nullptr) < 0);
+    // the allocation-free forward: the same validation, then the scratch limit, before any HIP call
+    EXPECT(fht_forward_noalloc(nullptr, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_FULL, 0, nullptr) < 0);
+    EXPECT(fht_forward_noalloc(p, FHT_F32, 300, 200, 299, p, FHT_F32, c, FHT_FULL, 0, nullptr) < 0);
+    EXPECT(fht_forward_noalloc(p, FHT_F32, 2048, 2048, 2048, p, FHT_F32, 4096, FHT_FULL, 0, nullptr) ==
+           FHT_ERR_UNSUPPORTED);
+    EXPECT(fht_engine_status(nullptr, nullptr) == FHT_ERR_INVALID);
+    EXPECT(fht_set_tile_rows(10, 48) == FHT_ERR_INVALID);
+    EXPECT(fht_set_tile_rows(2, 32) == FHT_ERR_INVALID);
     EXPECT(fht_range(p, FHT_F32, 300, 200, 300, 300, 2, 0, p, FHT_F32, c, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_range(p, FHT_F32, 300, 200, 300, 2, 2, 0, p, FHT_I32, c, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_range_scaled(p, FHT_F32, 300, 200, 300, 0, 1, 0, 0, 0, p, FHT_F32, c, p, 1u << 30, nullptr) < 0);

@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 KERNEL_UNITS = ["fht_misc", "fht_fwd_u8", "fht_fwd_i32", "fht_fwd_f32", "fht_fwd_u8_max", "fht_fwd_i32_max",
                 "fht_fwd_f32_max", "fht_adj_i32", "fht_adj_f32"]
-HOST_UNITS = ["fht_api", "fht_batch", "fht_lines", "fht_timing"]
+HOST_UNITS = ["fht_api", "fht_batch", "fht_lines", "fht_timing", "fht_noalloc"]
 
 
 def _run(cmd, **kw):
