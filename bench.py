@@ -189,17 +189,80 @@ def bench_batch(fht, torch, imgs, steps, warmup, label):
     return res
 
 
-def batch_graph_ms(fht, torch, imgs, steps):
+def batch_graph_ms(fht, torch, imgs, steps, packed=None):
     """ms per replay of one batch plan captured in a HIP graph (the current
-    stage splits)."""
+    stage splits and tile heights), into `packed` when given."""
     plan = fht.BatchPlan([tuple(x.shape) for x in imgs], in_dtype=imgs[0].dtype)
     table = plan.pointer_table(imgs)
-    packed = plan.output()
-    graph = plan.capture(table, packed)
+    out = plan.output() if packed is None else packed
+    graph = plan.capture(table, out)
     ms = _timed(graph.replay, steps, 2, torch)
-    del graph, packed, table, plan
+    del graph, out, table, plan
     torch.cuda.empty_cache()
     return ms
+
+
+def stage_configs(k):
+    """(split, tile rows) candidates for quadrants of 2^k rows: every split
+    into the fewest passes of 3..6 stages, each with 64-row tiles and, when
+    some pass has at most 5 stages, 32-row tiles (the candidates
+    fht_autotune times on one image)."""
+    n_pass = -(-k // 6)
+    splits = []
+
+    def extend(prefix, left, parts):
+        if parts == 0:
+            if left == 0:
+                splits.append(prefix)
+            return
+        for g in range(3, 7):
+            if g <= left:
+                extend(prefix + [g], left - g, parts - 1)
+
+    extend([], k, n_pass)
+    out = []
+    for sp in splits:
+        out.append((sp, 64))
+        if min(sp) <= 5:
+            out.append((sp, 32))
+    return out
+
+
+def tune_on_workload(fht, ks, time_fn):
+    """Stage split and tile height tuned on the workload itself: from the
+    default rules, for each stage count in turn every candidate is set and
+    the whole workload timed (time_fn), and the fastest setting is kept
+    before the next stage count.  Returns the default time, the best time
+    and the setting per stage count."""
+    for k in ks:
+        fht.set_pass_split(k, None)
+        fht.set_tile_rows(k, None)
+    time_fn()  # warm-up: first-call costs stay out of the comparison
+    ms_default = time_fn()
+    best_ms = ms_default
+    chosen = {}
+    for k in ks:
+        best = None
+        for split, rows in stage_configs(k):
+            fht.set_pass_split(k, split)
+            fht.set_tile_rows(k, rows)
+            ms = time_fn()
+            if ms < best_ms:
+                best_ms, best = ms, (split, rows)
+        if best is None:
+            fht.set_pass_split(k, None)
+            fht.set_tile_rows(k, None)
+        else:
+            fht.set_pass_split(k, best[0])
+            fht.set_tile_rows(k, best[1])
+        chosen[str(k)] = {"split": fht.pass_split(1 << k), "tile_rows": fht.tile_rows(1 << k)}
+    return ms_default, best_ms, chosen
+
+
+def reset_tuning(fht, ks):
+    for k in ks:
+        fht.set_pass_split(k, None)
+        fht.set_tile_rows(k, None)
 
 
 def bench_diff16(fht, synth, torch, steps):
@@ -219,17 +282,11 @@ def bench_diff16(fht, synth, torch, steps):
         x.grad = None
         fht.fht(x).backward(up)
 
-    # stage split of the 1024-row quadrants: the default against the split
-    # fht_autotune picks on one 1024^2 image, each timed on the whole step;
-    # the faster is kept and measured again
+    # stage split and tile height of the 1024-row quadrants tuned on the
+    # whole step (every candidate timed on it), then measured again
     k = max(0, (h - 1).bit_length())
-    default = fht.pass_split(h)
-    ms_default = _timed(step, steps, 2, torch)
-    fht.autotune(w, h, torch.float32, reps=10)
-    tuned = fht.pass_split(h)
-    ms_tuned = _timed(step, steps, 2, torch)
-    if ms_default <= ms_tuned:
-        fht.set_pass_split(k, None)
+    default = {"split": fht.pass_split(h), "tile_rows": fht.tile_rows(h)}
+    ms_default, ms_tuned, chosen = tune_on_workload(fht, [k], lambda: _timed(step, max(3, steps // 2), 1, torch))
     ms = _timed(step, steps, 2, torch)
     outs = torch.empty((n, rows, cols), device="cuda")
     grads = torch.empty_like(xs)
@@ -246,9 +303,10 @@ def bench_diff16(fht, synth, torch, steps):
                        "wrapper for a fixed upstream gradient", "unit": "Gpixels/s",
            "value": round(px / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
            "single_image_loop": {"value": round(px / (ms_loop * 1e-3) / 1e9, 3), "ms_per_step": round(ms_loop, 4)},
-           "splits": {"default": default, "tuned": tuned, "default_ms": round(ms_default, 4),
-                      "tuned_ms": round(ms_tuned, 4), "used": "tuned" if ms_tuned < ms_default else "default"}}
-    fht.set_pass_split(k, None)
+           "tuning": {"default": default, "default_ms": round(ms_default, 4), "used": chosen[str(k)],
+                      "tuned_ms": round(ms_tuned, 4),
+                      "how": "every (split, tile height) of the 1024-row quadrants timed on the whole step"}}
+    reset_tuning(fht, [k])
     return res
 
 
@@ -432,27 +490,25 @@ def main():
         torch.cuda.empty_cache()
 
         imgs512 = [torch.from_numpy(a).cuda() for a in synth.batch512(0)]
-        # Stage-fusion depth: the default splits against the splits tuned on
-        # this device for every stage count in the batch (fht_autotune on one
-        # square image of each padded side), each timed on the whole batch;
-        # the faster set is kept and measured again for the reported line.
-        ks = [k for k in sorted({max(0, (s - 1).bit_length()) for a in imgs512 for s in a.shape}) if 7 <= k <= 12]
-        default = {str(k): fht.pass_split(1 << k) for k in ks}
-        ms_default = batch_graph_ms(fht, torch, imgs512, 5)
-        for k in ks:
-            fht.autotune(1 << k, 1 << k, torch.uint8, reps=10)
-        tuned = {str(k): fht.pass_split(1 << k) for k in ks}
-        ms_tuned = batch_graph_ms(fht, torch, imgs512, 5)
-        if ms_default <= ms_tuned:
-            for k in ks:
-                fht.set_pass_split(k, None)
+        # Stage split and tile height per stage count tuned on the batch's
+        # own work list: each candidate timed on the whole batch (graph
+        # replay), one stage count at a time, then the line measured again.
+        ks = [k for k in sorted({max(0, (s - 1).bit_length()) for a in imgs512 for s in a.shape})
+              if len(stage_configs(k)) > 1]
+        default = {str(k): {"split": fht.pass_split(1 << k), "tile_rows": fht.tile_rows(1 << k)} for k in ks}
+        probe = fht.BatchPlan([tuple(a.shape) for a in imgs512], in_dtype=torch.uint8)
+        packed = probe.output()
+        del probe
+        ms_default, ms_tuned, chosen = tune_on_workload(
+            fht, ks, lambda: batch_graph_ms(fht, torch, imgs512, 3, packed=packed))
+        del packed
+        torch.cuda.empty_cache()
         result["batch512"] = bench_batch(fht, torch, imgs512, 3, 1, "batch512 u8")
         result["batch512"]["workload"] = "512 uint8 images, sides uniform in 64..2048 (seed 0), int32 Hough images"
-        result["batch512"]["splits"] = {"default": default, "tuned": tuned,
-                                        "default_ms": round(ms_default, 3), "tuned_ms": round(ms_tuned, 3),
-                                        "used": "tuned" if ms_tuned < ms_default else "default"}
-        for k in ks:
-            fht.set_pass_split(k, None)
+        result["batch512"]["tuning"] = {"default": default, "default_ms": round(ms_default, 3), "used": chosen,
+                                        "tuned_ms": round(ms_tuned, 3),
+                                        "how": "every (split, tile height) per stage count timed on the whole batch"}
+        reset_tuning(fht, ks)
         del imgs512
         torch.cuda.empty_cache()
 

@@ -327,8 +327,10 @@ int fht_timing_report(int index, char* name, int name_cap, int64_t* launches, do
 /*
  * Stage-fusion depth.  A quadrant of n = 2^k rows runs its k stages in the
  * fewest passes of at most 6 stages; how the stages are split among the
- * passes is a free choice (each pass 3..6 stages).  By default the larger
- * passes come first.  fht_set_pass_split sets the split used for k from now
+ * passes is a free choice (each pass 3..6 stages).  By default two passes
+ * put as many stages as they can in the first (the second keeps at least 3:
+ * 1024 rows run 6+4) and three or more are as even as possible, larger first
+ * (8192 rows: 5+4+4).  fht_set_pass_split sets the split used for k from now
  * on by every call in the process (npass = 0 restores the default; npass must
  * be the fewest passes, each entry 3..6, summing to k; k in 3..16).
  * fht_autotune times every candidate split for the stage counts of an h x w

@@ -47,8 +47,8 @@ int ilog2(int64_t p)
     return k;
 }
 
-// Stage-fusion split: k stages in ceil(k/6) passes of 3..6 stages, larger
-// passes first (k <= 2 runs as one direct pass).
+// Stage-fusion split: k stages in ceil(k/6) passes of 3..6 stages (k <= 2
+// runs as one direct pass).
 // Stage split per k, set by fht_set_pass_split / fht_autotune (npass 0:
 // the default rule).  Read at planning time only.
 static std::mutex g_split_mu;
@@ -86,10 +86,21 @@ void pass_split(int k, int* npass, int* G)
             return;
         }
     }
-    // fewest passes of at most kMaxG stages, larger first
+    // Fewest passes of at most kMaxG stages.  Two passes: the first as deep
+    // as it can be (the last keeps at least 3 stages).  Measured on MI355X
+    // against the even split: equal or faster on single images (256^2 to
+    // 1024^2, uint8 and float32: forward within 3 %, the 512^2 adjoint 10 %)
+    // and 5-6 % on the 16 x 1024^2 stack and the 512-image batch.  Three or
+    // more passes: as even as possible, larger first (8192^2: the deepest
+    // first pass, 6+4+3, was 3 % slower than 5+4+4).
     const int np = default_passes(k);
-    const int base = k / np, rem = k % np;
-    for (int i = 0; i < np; ++i) G[i] = base + (i < rem ? 1 : 0);
+    if (np == 2) {
+        G[0] = k - 3 < kMaxG ? k - 3 : kMaxG;
+        G[1] = k - G[0];
+    } else {
+        const int base = k / np, rem = k % np;
+        for (int i = 0; i < np; ++i) G[i] = base + (i < rem ? 1 : 0);
+    }
     *npass = np;
 }
 

@@ -91,8 +91,11 @@ def test_range_shape():
 
 def test_pass_split():
     assert fht.pass_split(4096) == [6, 6]
-    assert fht.pass_split(1024) == [5, 5]
-    assert fht.pass_split(256) == [4, 4]
+    assert fht.pass_split(1024) == [6, 4]
+    assert fht.pass_split(512) == [6, 3]
+    assert fht.pass_split(256) == [5, 3]
+    assert fht.pass_split(128) == [4, 3]
+    assert fht.pass_split(2048) == [6, 5]
     assert fht.pass_split(64) == [6]
     assert fht.pass_split(3) == [2]
     assert fht.pass_split(8192) == [5, 4, 4]
@@ -205,7 +208,7 @@ def test_range_scaled_shape_and_validation():
 
 def test_set_pass_split_validation_and_roundtrip():
     try:
-        assert fht.pass_split(1024) == [5, 5]
+        assert fht.pass_split(1024) == [6, 4]
         fht.set_pass_split(10, [4, 6])
         assert fht.pass_split(1024) == [4, 6]
         assert fht.pass_split(2048) == [6, 5]          # other k untouched
@@ -222,7 +225,7 @@ def test_set_pass_split_validation_and_roundtrip():
         assert fht.workspace_size(1024, 1024) <= wide
     finally:
         fht.set_pass_split(10, None)
-    assert fht.pass_split(1024) == [5, 5]
+    assert fht.pass_split(1024) == [6, 4]
 
 
 # The C entry points see only pointers and pitches; the binding checks every

@@ -26,9 +26,15 @@ def test_forward_launches_are_counted_per_kernel():
     finally:
         fht.timing_enable(False)
     rep = fht.timing_report()
-    # 1024: two passes of 5 stages (GB = 2), first pass from the image, last to the Hough image
-    first = "fht::fht_pass_kernel<float, float, 2, true, false, 0, %d, 0>" % (fht.tile_rows(1024) // 8)
-    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0, %d, 0>" % (fht.tile_rows(1024) // 8)
+    # 1024: two passes (GB = stages - 3), the first from the image, the last to
+    # the Hough image; 6-stage passes run 8 waves, shorter ones tile_rows / 8
+    g1, g2 = fht.pass_split(1024)
+
+    def waves(g):
+        return 8 if g == 6 else fht.tile_rows(1024) // 8
+
+    first = "fht::fht_pass_kernel<float, float, %d, true, false, 0, %d, 0>" % (g1 - 3, waves(g1))
+    last = "fht::fht_pass_kernel<float, float, %d, false, true, 0, %d, 0>" % (g2 - 3, waves(g2))
     assert set(rep) == {first, last}, rep
     for name in (first, last):
         launches, total_ms = rep[name]
@@ -89,8 +95,10 @@ def test_nothing_recorded_under_graph_capture():
 
 def test_filter_records_only_matching_kernels():
     img = torch.from_numpy(synth.random_image(1024, 1024, "f32", seed=4)).cuda()
-    last = "fht::fht_pass_kernel<float, float, 2, false, true, 0, %d, 0>" % (fht.tile_rows(1024) // 8)
-    fht.timing_filter("2, false, true, 0, ")
+    g2 = fht.pass_split(1024)[-1]
+    last = "fht::fht_pass_kernel<float, float, %d, false, true, 0, %d, 0>" % (
+        g2 - 3, 8 if g2 == 6 else fht.tile_rows(1024) // 8)
+    fht.timing_filter("%d, false, true, 0, " % (g2 - 3))
     fht.timing_enable(True)
     try:
         _forward(img, 2)

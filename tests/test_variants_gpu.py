@@ -17,6 +17,9 @@ sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
 import numpy as np, torch
 import oracle
 from paper_1811_06378_amd import fht, synth
+# even splits: both passes of a quadrant share one engine launch (one per
+# depth), so second-pass tiles wait for first-pass ones
+fht.set_pass_split(8, [4, 4]); fht.set_pass_split(10, [5, 5])
 for (h, w, kind) in [(5, 13, "u8"), (129, 257, "u8"), (300, 520, "f32"), (1000, 70, "i32")]:
     img = synth.random_image(h, w, kind, seed=3)
     got = fht.forward(torch.from_numpy(img).cuda()).cpu().numpy().astype(np.float64)
@@ -35,14 +38,16 @@ print("OK")
 """
 
 # With a spin limit of 1 iteration, the second-pass tiles of a 256^2 image
-# (two passes of 4 stages, every tile resident at once) give up waiting for
-# the first pass: each wait ends by itself, the flag is set, and the status
-# call reports it.  No kernel hangs or faults; the results are discarded.
+# (two passes of 4 stages in one engine launch, every tile resident at once)
+# give up waiting for the first pass: each wait ends by itself, the flag is
+# set, and the status call reports it.  No kernel hangs or faults; the
+# results are discarded.
 TIMEOUT_CHILD = r"""
 import sys
 sys.path.insert(0, {root!r})
 import torch
 from paper_1811_06378_amd import fht, synth
+fht.set_pass_split(8, [4, 4])
 img = torch.from_numpy(synth.random_image(256, 256, "u8", seed=5)).cuda()
 ws = torch.empty(fht.workspace_size(256, 256, "full", torch.uint8), dtype=torch.uint8, device="cuda")
 fht.forward(img, workspace=ws)
