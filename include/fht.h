@@ -182,8 +182,11 @@ int fht_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int t, i
  * forward transform.
  *   grad_hough device, shape of fht_hough_shape(w, h, quads) of t, pitch
  *              ld_hough; fhtshift-ed when flags has FHT_FLAG_SHIFTED
- *   grad_img   device, h x w of t, pitch ld_img >= w; fully overwritten
+ *   grad_img   device, h x w of t, pitch ld_img >= w; fully overwritten (the
+ *              first quadrant's contribution is stored, the later ones are
+ *              added to it in place, in quadrant order)
  *   t          FHT_I32 or FHT_F32 (the accumulator type of the forward)
+ * The workspace holds the intermediate bands.
  */
 int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img, int64_t ld_img,
                 int w, int h, unsigned quads, unsigned flags, void* workspace, size_t ws_bytes,

@@ -696,18 +696,9 @@ int fht_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, size_t
     return FHT_OK;
 }
 
-// Adjoint workspace: the bands, then one h x w scratch image (row pitch w)
-// per selected quadrant after the first: the image passes of those quadrants
-// run together, each writing its own scratch image, and the first quadrant's
-// image pass then adds them to its own values in quadrant order as it stores
-// the gradient.
-static size_t scratch_image_bytes(int w, int h) { return ((size_t)w * (size_t)h * 4 + 255) / 256 * 256; }
-
-static size_t adjoint_workspace(QuadGeom* gs, const int* qs, int nq, int w, int h)
-{
-    (void)qs;
-    return layout_bands(gs, nq, 4, 0) + (size_t)(nq > 1 ? nq - 1 : 0) * scratch_image_bytes(w, h);
-}
+// Adjoint workspace: the bands.  The image passes add their contributions
+// to the image gradient itself, in quadrant order (run_adjoint).
+static size_t adjoint_workspace(QuadGeom* gs, int nq) { return layout_bands(gs, nq, 4, 0); }
 
 int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* bytes)
 {
@@ -720,7 +711,7 @@ int fht_adjoint_workspace_size(int w, int h, unsigned quads, int t, size_t* byte
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    *bytes = adjoint_workspace(gs, qs, nq, w, h);
+    *bytes = adjoint_workspace(gs, nq);
     return FHT_OK;
 }
 
@@ -971,7 +962,7 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
 
 // Adjoint of several same-size images, launched together (their passes of
 // one kind share a launch).  Each image has its own gradient, output and
-// workspace slice (bands, then the scratch images of quadrants 2..4).
+// workspace slice (the bands).
 struct AdjImage {
     const void* grad;
     void* img;
@@ -1003,86 +994,90 @@ int run_adjoint(const AdjImage* ims, int m, int t, int64_t ld_hough, int64_t ld_
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    const size_t bands = layout_bands(gs, nq, 4, 0);
-    // image targets: every quadrant after the first writes its own scratch
-    // image; the first quadrant's image pass runs last, reads them at its
-    // output cells and stores ((q1 + q2) + q3) + q4, the contributions in
-    // quadrant order
+    layout_bands(gs, nq, 4, 0);  // each quadrant's band offsets in the workspace
+    // Image passes in steps, in quadrant order: a mirror pair (quadrants 1
+    // and 2, or 3 and 4, both with pass kernels), whose tiles one workgroup
+    // computes together, or one quadrant.  The first step stores its values
+    // in the image gradient; every later one adds its own to what is stored
+    // there, so the image receives ((q1 + q2) + q3) + q4, the contributions
+    // in quadrant order (a pair's kernel adds the mirrored member's values
+    // first: (s + q3) + q4).
+    struct Step {
+        int u, m;  // pair: unmirrored and mirrored quadrant indices; single: u, m = -1
+    };
+    Step steps[4];
+    int n_steps = 0;
+    for (int i = 0; i < nq;) {
+        if (i + 1 < nq && (qs[i] == 1 || qs[i] == 3) && qs[i + 1] == qs[i] + 1 && gs[i].k > 2 && gs[i + 1].k > 2) {
+            // quadrant 1 and 4 are unmirrored, 2 and 3 mirrored
+            steps[n_steps++] = qs[i] == 1 ? Step{i, i + 1} : Step{i + 1, i};
+            i += 2;
+        } else {
+            steps[n_steps++] = Step{i, -1};
+            i += 1;
+        }
+    }
     AdjDesc descs[kStackGroup][4][4];
-    const int last = 0;  // the quadrant whose image pass runs last
     for (int k = 0; k < m; ++k) {
-        unsigned char* scratch = ims[k].ws + bands;
-        const void* parts[3] = {nullptr, nullptr, nullptr};
-        int n_part = 0;
         for (int i = 0; i < nq; ++i) {
-            void* target = ims[k].img;
-            int64_t target_ld = ld_img;
-            if (i > 0) {
-                target = scratch;
-                target_ld = w;
-                parts[n_part++] = scratch;
-                scratch += scratch_image_bytes(w, h);
-            }
             int base, sign, skip, ra, rb;
             placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
-            for (int p = 0; p < gs[i].npass; ++p) {
-                AdjDesc& d = descs[k][i][p];
-                d = make_adj_desc(gs[i], p, ims[k].grad, ld_hough, target, target_ld, w, h, ims[k].ws, base, sign,
-                                  skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
-            }
+            for (int p = 0; p < gs[i].npass; ++p)
+                descs[k][i][p] = make_adj_desc(gs[i], p, ims[k].grad, ld_hough, ims[k].img, ld_img, w, h, ims[k].ws,
+                                               base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
         }
-        if (nq > 1) {
-            AdjDesc& d = descs[k][0][0];
-            d.accumulate = 1;
-            d.n_part = n_part;
-            d.part_ld = w;
-            for (int j = 0; j < 3; ++j) d.part[j] = parts[j];
+        for (int st = 1; st < n_steps; ++st) {
+            const int members[2] = {steps[st].u, steps[st].m};
+            for (int i : members) {
+                if (i < 0) continue;
+                descs[k][i][0].accumulate = 1;
+            }
         }
     }
     int maxp = 0;
     for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
-    // adjoint passes in reverse order, every image's and quadrant's pass of
-    // one kind in one launch, except the first quadrant's image pass; then
-    // the other direct (tiny) quadrants; then the first quadrant's image
-    // pass, once every other contribution is in place
-    auto launch_kind = [&](int p, bool only_last) -> int {
+    // band passes (p >= 1) in reverse order, every image's and quadrant's
+    // pass of one kind in one launch
+    for (int p = maxp - 1; p >= 1; --p) {
         for (int G = 3; G <= kMaxG; ++G) {
             for (int first = 0; first < 2; ++first) {
                 AdjLaunch L{};
                 for (int k = 0; k < m; ++k)
-                    for (int i = 0; i < nq; ++i) {
-                        if (p == 0 && (i == last) != only_last) continue;
-                        if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G &&
-                            (p == gs[i].npass - 1) == (first == 1))
+                    for (int i = 0; i < nq; ++i)
+                        if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first == 1))
                             L.d[L.nd++] = descs[k][i][p];
-                    }
                 if (L.nd == 0) continue;
                 hipError_t e = launch_adjoint_pass(L, t, s);
                 if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
             }
         }
-        return FHT_OK;
-    };
-    auto launch_direct_of = [&](int i) -> int {
-        for (int k = 0; k < m; ++k) {
+    }
+    // the image-pass steps, each once the previous one has stored
+    for (int st = 0; st < n_steps; ++st) {
+        const Step& S = steps[st];
+        hipError_t e = hipSuccess;
+        if (S.m >= 0) {
             AdjLaunch L{};
-            L.d[0] = descs[k][i][0];
-            L.nd = 1;
-            hipError_t e = launch_adjoint_direct(L, gs[i].k, t, s);
-            if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
+            for (int k = 0; k < m; ++k) {
+                L.d[L.nd++] = descs[k][S.u][0];
+                L.d[L.nd++] = descs[k][S.m][0];
+            }
+            e = launch_adjoint_pair(L, t, s);
+        } else if (gs[S.u].k > 2) {
+            AdjLaunch L{};
+            for (int k = 0; k < m; ++k) L.d[L.nd++] = descs[k][S.u][0];
+            e = launch_adjoint_pass(L, t, s);
+        } else {
+            for (int k = 0; k < m && e == hipSuccess; ++k) {
+                AdjLaunch L{};
+                L.d[0] = descs[k][S.u][0];
+                L.nd = 1;
+                e = launch_adjoint_direct(L, gs[S.u].k, t, s);
+            }
         }
-        return FHT_OK;
-    };
-    for (int p = maxp - 1; p >= 0; --p) {
-        int rc = launch_kind(p, false);
-        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e, "adjoint image pass launch");
     }
-    for (int i = 1; i < nq; ++i) {
-        if (gs[i].k > 2) continue;
-        int rc = launch_direct_of(i);
-        if (rc) return rc;
-    }
-    return gs[last].k > 2 ? launch_kind(0, true) : launch_direct_of(last);
+    return FHT_OK;
 }
 
 }  // namespace fht
@@ -1098,7 +1093,7 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     const int nq = selected_quads(quads, qs);
     QuadGeom gs[4];
     for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
-    const size_t need = adjoint_workspace(gs, qs, nq, w, h);
+    const size_t need = adjoint_workspace(gs, nq);
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     if (workspace && ((uintptr_t)workspace & 255)) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");

@@ -946,43 +946,27 @@ __device__ __forceinline__ void adj_patch_hough(const AdjDesc& d, int s_row, int
 }
 
 // Image-gradient stores.  Without accumulate the value is written; with it
-// the result is ((value + part[0]) + part[1]) + part[2]: this quadrant's
-// contribution first, then the other quadrants' partial images in quadrant
-// order (pi: the element's index in the partial images).  Every partial is
-// loaded before the first add, so the loads of a row go out together.
+// the value is added to the gradient already stored there (the earlier
+// quadrants' sum s, giving s + value).
 template <typename T, bool ACC>
-__device__ __forceinline__ void acc_store8(const AdjDesc& d, T* p, int64_t pi, const T (&v)[8])
+__device__ __forceinline__ void acc_store8(T* p, const T (&v)[8])
 {
-    if constexpr (!ACC) {
+    if constexpr (ACC) {
+        T o[8];
+        load8<T>(p, o);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) o[c] = o[c] + v[c];
+        store8<T>(p, o);
+    } else {
         store8<T>(p, v);
-        return;
     }
-    T t0[8], t1[8], t2[8];
-    load8<T>(reinterpret_cast<const T*>(d.part[0]) + pi, t0);
-    if (d.n_part > 1) load8<T>(reinterpret_cast<const T*>(d.part[1]) + pi, t1);
-    if (d.n_part > 2) load8<T>(reinterpret_cast<const T*>(d.part[2]) + pi, t2);
-    T o[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) o[c] = v[c] + t0[c];
-    if (d.n_part > 1)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) o[c] = o[c] + t1[c];
-    if (d.n_part > 2)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) o[c] = o[c] + t2[c];
-    store8<T>(p, o);
 }
 
 template <typename T, bool ACC>
-__device__ __forceinline__ T acc_value(const AdjDesc& d, int64_t pi, T v)
+__device__ __forceinline__ void acc_store1(T* p, T v)
 {
-    if constexpr (!ACC) return v;
-    // fixed indices: a loop over part[k] would index the descriptor
-    // dynamically and move it to scratch memory
-    T o = v + reinterpret_cast<const T*>(d.part[0])[pi];
-    if (d.n_part > 1) o = o + reinterpret_cast<const T*>(d.part[1])[pi];
-    if (d.n_part > 2) o = o + reinterpret_cast<const T*>(d.part[2])[pi];
-    return o;
+    if constexpr (ACC) *p = *p + v;
+    else *p = v;
 }
 
 template <typename T, int GB>
@@ -1023,20 +1007,19 @@ __device__ __forceinline__ void adj_exchange(T (&b)[8][8], T (&a)[8][8], T* lds,
     }
 }
 
-// ACC: the image pass that adds the other quadrants' partial images (the
-// descriptors' accumulate flag); a separate instantiation keeps that code
-// out of every other adjoint kernel.
-template <typename T, int GB, bool FIRST, bool LAST, bool ACC = false>
-__device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* lds)
+// One adjoint tile up to its stores: the forward pass's output rows of row
+// tile rt at the window whose first own column is xi = x_lo (8 waves, wave
+// 0..7 of them, exchange in lds), through the exchange and the stages, into
+// a: lane l's register c is column xi = x_lo - 2^G + 8l + c of tile rows
+// 8*wave .. 8*wave + 7.  Every wave reaches the exchange's barriers.
+template <typename T, int GB, bool FIRST>
+__device__ __forceinline__ void adj_compute(const AdjDesc& d, int rt, int x_lo, T* lds, int wave, int lane,
+                                            T (&a)[8][8])
 {
     constexpr int G = 3 + GB;
-    constexpr int VW = kWinCols - (1 << G);
     constexpr int nmini_tile = 1 << (6 - G);
-    const int lane = threadIdx.x & 63;
-    const int wave = uniform(threadIdx.x >> 6);
     const int j0 = d.j0;
     const int n_mini = d.n >> G;
-    const int x_lo = d.x_start + win * VW;
     const int xw0 = x_lo - (1 << G);             // xi of the tile's column 0 (halo first)
     constexpr bool first = FIRST;                // reads the Hough gradient (else a band)
     const int W = d.W;
@@ -1096,11 +1079,30 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
         }
     }
 
-    T a[8][8];
     adj_exchange<T, GB>(b, a, lds, wave, lane);
     adj_stage<T, 2>(a);
     adj_stage<T, 1>(a);
     adj_stage<T, 0>(a);
+}
+
+// ACC: the image pass that adds its values to the stored gradient (the
+// descriptors' accumulate flag); a separate instantiation keeps that code
+// out of every other adjoint kernel.
+template <typename T, int GB, bool FIRST, bool LAST, bool ACC = false>
+__device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* lds)
+{
+    constexpr int G = 3 + GB;
+    constexpr int VW = kWinCols - (1 << G);
+    constexpr int nmini_tile = 1 << (6 - G);
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform(threadIdx.x >> 6);
+    const int j0 = d.j0;
+    const int n_mini = d.n >> G;
+    const int x_lo = d.x_start + win * VW;
+    const int xw0 = x_lo - (1 << G);
+    const int W = d.W;
+    T a[8][8];
+    adj_compute<T, GB, FIRST>(d, rt, x_lo, lds, wave, lane, a);
 
     // ---- store row m of each mini transform at its offset u*m
     const int wc0 = 8 * lane;
@@ -1155,13 +1157,12 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
                 T v[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) v[c] = d.mirror ? a[r][7 - c] : a[r][c];
-                acc_store8<T, ACC>(d, p + e0, (int64_t)R * d.part_ld + e0, v);
+                acc_store8<T, ACC>(p + e0, v);
             } else {
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int e = run_col(e0, c, W, d.mirror);
-                    if (rel + c < cols && e < cols)
-                        p[e] = acc_value<T, ACC>(d, (int64_t)R * d.part_ld + e, a[r][c]);
+                    if (rel + c < cols && e < cols) acc_store1<T, ACC>(p + e, a[r][c]);
                 }
             }
         }
@@ -1177,13 +1178,12 @@ __device__ __forceinline__ void adj_tile(const AdjDesc& d, int rt, int win, T* l
             T v[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) v[r] = a[r][c];
-            const int64_t pi = (int64_t)e * d.part_ld + R0;
             if (all_cols) {
-                acc_store8<T, ACC>(d, p, pi, v);
+                acc_store8<T, ACC>(p, v);
             } else {
 #pragma unroll
                 for (int r = 0; r < 8; ++r)
-                    if (R0 + r < d.img_w) p[r] = acc_value<T, ACC>(d, pi + r, v[r]);
+                    if (R0 + r < d.img_w) acc_store1<T, ACC>(p + r, v[r]);
             }
         }
     }
@@ -1196,6 +1196,125 @@ __global__ __launch_bounds__(kThreads, 4) void fht_adj_pass_kernel(const AdjLaun
     const AdjDesc d = L.d[blockIdx.z];  // a private copy: its fields stay in registers across the stores
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
     adj_tile<T, GB, FIRST, LAST, ACC>(d, blockIdx.y, blockIdx.x, lds);
+}
+
+// Image pass of a mirror pair of quadrants (1 and 2, or 3 and 4) over the
+// same image region, one 16-wave workgroup per tile.  Descriptor 2z is the
+// unmirrored quadrant U (waves 0-7), 2z + 1 the mirrored one M (waves 8-15);
+// both have the same n, stage split, row tiles and image columns.  U's
+// window w covers image columns [c0, c0 + VW), c0 = w * VW, at xi = x; M
+// covers the same columns at xi = W - x, from its own first column
+// xi = W - c0 - VW + 1.  After the stages M's values go through LDS (the two
+// exchange regions, free again) to the U lane holding the same image cell,
+// and U's waves store M + U, or with ACC (s + M) + U where s is the
+// gradient already stored there (the earlier quadrants' sum, in quadrant
+// order).  Both halves run the same loads, exchange barriers and stages.
+template <typename T, int GB, bool FIRST, bool ACC>
+__global__ __launch_bounds__(2 * kThreads, 4) void fht_adj_pair_kernel(const AdjLaunch L)
+{
+    __shared__ T lds[kTileRows * kLdsRow];
+    constexpr int G = 3 + GB;
+    constexpr int VW = kWinCols - (1 << G);
+    constexpr int nmini_tile = 1 << (6 - G);
+    constexpr int kCbRow = kWinCols;  // combine buffer: one row per tile row
+    static_assert(kTileRows * kCbRow <= kTileRows * kLdsRow, "combine buffer exceeds the exchange regions");
+    // the whole workgroup leaves together (U's counts bound the pair)
+    if ((int)blockIdx.x >= L.d[2 * blockIdx.z].n_windows || (int)blockIdx.y >= L.d[2 * blockIdx.z].n_row_tiles)
+        return;
+    const int half = uniform((int)threadIdx.x >> 9);
+    const int wave = uniform(((int)threadIdx.x >> 6) & 7);
+    const int lane = threadIdx.x & 63;
+    const AdjDesc d = L.d[2 * blockIdx.z + half];
+    const int c0 = blockIdx.x * VW;
+    const int x_lo = half == 0 ? c0 : d.W - c0 - VW + 1;
+    T a[8][8];
+    adj_compute<T, GB, FIRST>(d, blockIdx.y, x_lo, lds + half * (kTileRows / 2 * kLdsRow), wave, lane, a);
+    __syncthreads();  // every wave is done with both exchange regions
+
+    // image column of register c: U lane l, c0 - 2^G + 8l + c; M lane l,
+    // c0 + 511 - 8l - c.  Offsets o = column - c0 in [0, VW) are the lanes
+    // with 8l >= 2^G (the others hold the halo).
+    const bool own = 8 * lane >= (1 << G);
+    T* cb = lds + wave * 8 * kCbRow;
+    if (half == 1 && own) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            T* q = cb + r * kCbRow + (kWinCols - 8) - 8 * lane;  // offsets 504 - 8l .. 511 - 8l
+#pragma unroll
+            for (int c = 0; c < 8; ++c) q[c] = a[r][7 - c];
+        }
+    }
+    __syncthreads();
+    if (half == 1 || !own) return;
+
+    // ---- stores (the image pass: j0 = 0, row m of mini transform mu is
+    // tile row (mu << G) + m).  M's values are read from LDS next to their
+    // use, a row (or column) at a time, so that only U's tile stays in
+    // registers.
+    const T* mrow = cb + 8 * lane - (1 << G);  // M's value at U's register (r, c): mrow[r * kCbRow + c]
+    const int xi = c0 - (1 << G) + 8 * lane;   // image column of register 0
+    const int tr0 = wave * 8;
+    const int mu = blockIdx.y * nmini_tile + (tr0 >> G);
+    if (mu >= (d.n >> G)) return;
+    const int cols = d.dst_kind == 1 ? d.img_w : d.img_h;
+    if (xi >= cols) return;
+    const bool full_run = xi + 8 <= cols;
+    if (d.dst_kind == 1) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int R = (mu << G) + ((tr0 + r) & ((1 << G) - 1));
+            if (R >= d.img_h) continue;
+            T mv[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) mv[c] = mrow[r * kCbRow + c];
+            T* p = reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + xi;
+            if (full_run) {
+                T v[8];
+                if constexpr (ACC) {
+                    load8<T>(p, v);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) v[c] = (v[c] + mv[c]) + a[r][c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) v[c] = mv[c] + a[r][c];
+                }
+                store8<T>(p, v);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (xi + c < cols) p[c] = ACC ? (p[c] + mv[c]) + a[r][c] : mv[c] + a[r][c];
+            }
+        }
+    } else {
+        // transposed image: tile rows R0..R0+7 are image columns, register c
+        // is image row xi + c
+        const int R0 = (mu << G) + (tr0 & ((1 << G) - 1));
+        const bool all_cols = R0 + 8 <= d.img_w;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (xi + c >= cols) continue;
+            T mv[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) mv[r] = mrow[r * kCbRow + c];
+            T* p = reinterpret_cast<T*>(d.dst) + (long long)(xi + c) * d.dst_ld + R0;
+            if (all_cols) {
+                T v[8];
+                if constexpr (ACC) {
+                    load8<T>(p, v);
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v[r] = (v[r] + mv[r]) + a[r][c];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v[r] = mv[r] + a[r][c];
+                }
+                store8<T>(p, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (R0 + r < d.img_w) p[r] = ACC ? (p[r] + mv[r]) + a[r][c] : mv[r] + a[r][c];
+            }
+        }
+    }
 }
 
 // -------------------------------------------- direct form for n <= 4 rows
@@ -1309,8 +1428,7 @@ __global__ __launch_bounds__(256) void fht_adj_direct_kernel(const AdjLaunch L)
     const T v = adj_direct<T, 0, K>(d, R, x);
     T* p = d.dst_kind == 2 ? reinterpret_cast<T*>(d.dst) + (long long)x * d.dst_ld + R
                            : reinterpret_cast<T*>(d.dst) + (long long)R * d.dst_ld + x;
-    const int64_t pi = d.dst_kind == 2 ? (int64_t)x * d.part_ld + R : (int64_t)R * d.part_ld + x;
-    *p = d.accumulate ? acc_value<T, true>(d, pi, v) : v;
+    *p = d.accumulate ? *p + v : v;
 }
 
 // ------------------------------------------------ angle-range adjoint tail

@@ -76,10 +76,8 @@ struct AdjDesc {
     int64_t src_ld, dst_ld;
     int src_kind;         // 0: Hough rows, 1: band
     int dst_kind;         // 0: band, 1: image, 2: image transposed
-    int accumulate;       // image destination: 1 = store ((value + part[0]) + part[1]) + part[2]
-    int n_part;           //   over the first n_part (1..3) partial images (the other
-    int64_t part_ld;      //   quadrants' contributions, image layout h x w, row pitch
-    const void* part[3];  //   part_ld); 0 = store the value
+    int accumulate;       // image destination: 1 = add the value to the one stored there
+                          //   (the earlier quadrants' sum), 0 = store it
     int img_w, img_h;
     int n, W, j0, G, mirror;
     int src_off, src_bw;
@@ -135,6 +133,7 @@ hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int
 hipError_t launch_table_direct(const EngineGroup* table, int n_groups, int n_items, int in_t, int acc_t,
                                hipStream_t s);
 hipError_t launch_adjoint_pass(const AdjLaunch& L, int t, hipStream_t s);
+hipError_t launch_adjoint_pair(const AdjLaunch& L, int t, hipStream_t s);
 hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t rows, int64_t cols, int64_t ld, int elem_bytes, hipStream_t s);
 hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out, int elem_bytes,

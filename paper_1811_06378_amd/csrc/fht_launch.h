@@ -160,7 +160,7 @@ hipError_t launch_adj_pass_g(const AdjLaunch& L, hipStream_t s)
     }
     const bool first = L.d[0].src_kind == 0, last = L.d[0].dst_kind != 0;
     const dim3 grid(wx, ry, L.nd);
-    // image passes that add partial images run their own instantiation; all
+    // image passes that add to the stored gradient run their own instantiation; all
     // descriptors of a launch agree
     const bool acc = last && L.d[0].accumulate != 0;
     for (int i = 1; i < L.nd; ++i)
@@ -189,6 +189,48 @@ hipError_t launch_adj_pass_t(const AdjLaunch& L, hipStream_t s)
     case 4: return launch_adj_pass_g<T, 1>(L, s);
     case 5: return launch_adj_pass_g<T, 2>(L, s);
     case 6: return launch_adj_pass_g<T, 3>(L, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Mirror-pair image passes: descriptors (U, M) at 2z and 2z + 1, U
+// unmirrored and M mirrored, of one quadrant geometry each (same n, stage
+// split, row tiles, windows and image target); all pairs share G, the
+// first-pass flag and the accumulate flag.
+template <typename T, int GB>
+hipError_t launch_adj_pair_g(const AdjLaunch& L, hipStream_t s)
+{
+    if (L.nd < 2 || (L.nd & 1)) return hipErrorInvalidValue;
+    int wx = 1, ry = 1;
+    for (int i = 0; i < L.nd; i += 2) {
+        const AdjDesc& u = L.d[i];
+        const AdjDesc& m = L.d[i + 1];
+        if (u.mirror != 0 || m.mirror != 1 || u.n != m.n || u.G != m.G || u.j0 != 0 || m.j0 != 0 ||
+            u.n_windows != m.n_windows || u.n_row_tiles != m.n_row_tiles || u.dst_kind == 0 ||
+            u.dst_kind != m.dst_kind || u.dst != m.dst || u.W != m.W || u.x_start != 0 ||
+            u.src_kind != L.d[0].src_kind || m.src_kind != L.d[0].src_kind ||
+            u.accumulate != L.d[0].accumulate || u.G != L.d[0].G)
+            return hipErrorInvalidValue;
+        wx = u.n_windows > wx ? u.n_windows : wx;
+        ry = u.n_row_tiles > ry ? u.n_row_tiles : ry;
+    }
+    const bool first = L.d[0].src_kind == 0, acc = L.d[0].accumulate != 0;
+    const dim3 grid(wx, ry, L.nd / 2), block(2 * kThreads);
+    if (first && acc) hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, true, true>), grid, block, 0, s, L);
+    else if (first) hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, true, false>), grid, block, 0, s, L);
+    else if (acc) hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, false, true>), grid, block, 0, s, L);
+    else hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, false, false>), grid, block, 0, s, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_pair_t(const AdjLaunch& L, hipStream_t s)
+{
+    switch (L.d[0].G) {
+    case 3: return launch_adj_pair_g<T, 0>(L, s);
+    case 4: return launch_adj_pair_g<T, 1>(L, s);
+    case 5: return launch_adj_pair_g<T, 2>(L, s);
+    case 6: return launch_adj_pair_g<T, 3>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -228,6 +270,8 @@ FHT_DECLARE_FWD(f32)
 #undef FHT_DECLARE_FWD
 hipError_t launch_adj_pass_i32(const AdjLaunch& L, hipStream_t s);
 hipError_t launch_adj_pass_f32(const AdjLaunch& L, hipStream_t s);
+hipError_t launch_adj_pair_i32(const AdjLaunch& L, hipStream_t s);
+hipError_t launch_adj_pair_f32(const AdjLaunch& L, hipStream_t s);
 hipError_t launch_adj_direct_i32(const AdjLaunch& L, int k, hipStream_t s);
 hipError_t launch_adj_direct_f32(const AdjLaunch& L, int k, hipStream_t s);
 

@@ -120,6 +120,22 @@ hipError_t launch_adjoint_pass(const AdjLaunch& L, int t, hipStream_t s)
     return e;
 }
 
+hipError_t launch_adjoint_pair(const AdjLaunch& L, int t, hipStream_t s)
+{
+    int slot = -1;
+    if (timing_on()) {
+        // the kernel's template arguments: type, GB, first, accumulate
+        std::string name = kernel_name("fht_adj_pair_kernel", -1, t, L.d[0].G - 3, L.d[0].src_kind == 0,
+                                       L.d[0].accumulate != 0);
+        slot = timing_begin(name, s);
+    }
+    hipError_t e = hipErrorInvalidValue;
+    if (t == 1) e = launch_adj_pair_i32(L, s);
+    if (t == 2) e = launch_adj_pair_f32(L, s);
+    timing_end(slot, s);
+    return e;
+}
+
 hipError_t launch_adjoint_direct(const AdjLaunch& L, int k, int t, hipStream_t s)
 {
     if (t == 1) return launch_adj_direct_i32(L, k, s);

@@ -39,8 +39,13 @@ def test_adjoint_float(h, w):
     assert_close_fp(got, oracle.adjoint_full(g, w, h), oracle.adjoint_full(np.abs(g), w, h), "adjoint f32")
 
 
-@pytest.mark.parametrize("h,w", [(8, 8), (16, 24), (300, 520)])
-@pytest.mark.parametrize("quads", [[1], [2], [3], [4], [2, 4]])
+# image passes run in quadrant order, as mirror pairs (1 and 2, 3 and 4) or
+# single quadrants, the later ones adding to the stored gradient: every mix
+SUBSETS = [[1], [2], [3], [4], [2, 4], [1, 2], [3, 4], [2, 3], [1, 2, 3], [1, 2, 4], [1, 3, 4], [2, 3, 4]]
+
+
+@pytest.mark.parametrize("h,w", [(8, 8), (16, 24), (33, 100), (300, 520)])
+@pytest.mark.parametrize("quads", SUBSETS)
 def test_adjoint_quadrant_subsets(h, w, quads):
     g = _grad(h, w, "i32", seed=2, quads=quads)
     got = host(P.adjoint(dev(g), w, h, quads=quads))
@@ -52,6 +57,24 @@ def test_adjoint_quadrant_subsets(h, w, quads):
         want = want + oracle.adjoint_quadrant(g[r:r + n].astype(np.float64), w, h, q)
         r += n
     assert_equal(got.astype(np.float64), want, "adjoint quads %s" % quads)
+
+
+@pytest.mark.parametrize("h,w", [(3, 40), (40, 3), (16, 24), (100, 33), (300, 520)])
+@pytest.mark.parametrize("quads", SUBSETS)
+def test_adjoint_quadrant_subsets_float_order(h, w, quads):
+    """float32 subsets bit for bit: each quadrant's binary32 transpose, summed
+    in binary32 in quadrant order."""
+    g = _grad(h, w, "f32", seed=6, quads=quads)
+    got = host(P.adjoint(dev(g), w, h, quads=quads))
+    hp, wp = oracle.next_pow2(h), oracle.next_pow2(w)
+    want = None
+    r = 0
+    for q in sorted(quads):
+        n = hp if q <= 2 else wp
+        c = oracle.adjoint_quadrant(g[r:r + n], w, h, q, single=True).astype(np.float32)
+        want = c if want is None else (want + c).astype(np.float32)
+        r += n
+    assert_equal(got.astype(np.float64), want.astype(np.float64), "adjoint f32 quads %s" % quads)
 
 
 @pytest.mark.parametrize("h,w", [(8, 8), (13, 5), (300, 520)])
