@@ -194,14 +194,16 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
 
 /*
  * fht_adjoint of a stack of n same-size gradients (the backward of a stack
- * of images), with up to 4 images' passes of one kind in each launch: small
- * images fill the chip together where one alone leaves it mostly idle.
+ * of images): one launch per pass kind covers a whole group of images (as
+ * many as keep their bands within 2 GiB, at most 8192), so small images fill
+ * the chip together where one alone leaves it mostly idle.
  * Image i's gradient starts grad_stride elements after image i-1's
  * (grad_stride >= rows * ld_hough when n > 1), and its output img_stride
  * elements after (img_stride >= h * ld_img when n > 1).  Every other
  * argument as fht_adjoint; results equal n calls of fht_adjoint bit for bit.
  * The workspace (>= fht_adjoint_stack_workspace_size, 256-byte aligned)
- * holds min(n, 4) single-image workspaces.
+ * holds one single-image workspace (rounded up to 256 bytes) per image of a
+ * group.
  */
 int fht_adjoint_stack_workspace_size(int w, int h, unsigned quads, int t, int n, size_t* bytes);
 int fht_adjoint_stack(const void* grad_hough, int t, int64_t ld_hough, int64_t grad_stride,
@@ -267,6 +269,10 @@ int fht_range_adjoint(const void* grad, int t, int64_t ld_grad, int S1, int S, i
  *   dense, ld = w_i); hough is the packed output; workspace is 256-byte
  *   aligned, at least *ws_bytes.  A plan is immutable: concurrent calls on
  *   different streams need their own workspace.
+ * fht_batch_forward_stack: as fht_batch_forward for a plan of n equal
+ *   sizes (FHT_ERR_INVALID otherwise), with image i dense at base +
+ *   i * stride_bytes (stride_bytes >= one image when n > 1): no device
+ *   pointer array, so nothing is copied from the host per call.
  * fht_batch_plan_destroy: frees the plan's tables (NULL is a no-op).
  */
 typedef struct fht_batch_plan fht_batch_plan;
@@ -275,6 +281,8 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
                           int64_t* out_offsets);
 int fht_batch_forward(const fht_batch_plan* plan, const void* const* imgs, void* hough,
                       void* workspace, size_t ws_bytes, void* stream);
+int fht_batch_forward_stack(const fht_batch_plan* plan, const void* base, int64_t stride_bytes, void* hough,
+                            void* workspace, size_t ws_bytes, void* stream);
 int fht_batch_plan_destroy(fht_batch_plan* plan);
 
 /*

@@ -960,15 +960,28 @@ AdjDesc make_adj_desc(const QuadGeom& g, int p, const void* grad, int64_t ld_gra
     return d;
 }
 
-// Adjoint of several same-size images, launched together (their passes of
-// one kind share a launch).  Each image has its own gradient, output and
-// workspace slice (the bands).
-struct AdjImage {
+// Adjoint of a stack of same-size images in one set of launches: image i's
+// gradient, output and workspace slice (its bands) sit i * grad_step,
+// i * img_step and i * ws_step bytes after image 0's; the launches run the
+// image index on their z axis.
+struct AdjStack {
     const void* grad;
     void* img;
     unsigned char* ws;
+    int64_t grad_step, img_step, ws_step;
+    int m;
 };
-constexpr int kStackGroup = kMaxAdjDescs / 4;
+
+// Images per stack group: their bands within 2 GiB, at most 8192 (the grid's
+// z extent, 4 descriptors per image, stays below 2^15).
+static int stack_group(size_t slice, int n)
+{
+    const size_t budget = size_t(2) << 30;
+    size_t g = slice ? budget / slice : (size_t)n;
+    if (g > 8192) g = 8192;
+    if (g > (size_t)n) g = (size_t)n;
+    return g < 1 ? 1 : (int)g;
+}
 
 int check_adjoint_args(const void* grad_hough, int t, int64_t ld_hough, const void* grad_img, int64_t ld_img, int w,
                        int h, unsigned quads, unsigned flags)
@@ -987,7 +1000,7 @@ int check_adjoint_args(const void* grad_hough, int t, int64_t ld_hough, const vo
     return FHT_OK;
 }
 
-int run_adjoint(const AdjImage* ims, int m, int t, int64_t ld_hough, int64_t ld_img, int w, int h, unsigned quads,
+int run_adjoint(const AdjStack& S, int t, int64_t ld_hough, int64_t ld_img, int w, int h, unsigned quads,
                 unsigned flags, hipStream_t s)
 {
     int qs[4];
@@ -1017,35 +1030,35 @@ int run_adjoint(const AdjImage* ims, int m, int t, int64_t ld_hough, int64_t ld_
             i += 1;
         }
     }
-    AdjDesc descs[kStackGroup][4][4];
-    for (int k = 0; k < m; ++k) {
-        for (int i = 0; i < nq; ++i) {
-            int base, sign, skip, ra, rb;
-            placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
-            for (int p = 0; p < gs[i].npass; ++p)
-                descs[k][i][p] = make_adj_desc(gs[i], p, ims[k].grad, ld_hough, ims[k].img, ld_img, w, h, ims[k].ws,
-                                               base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
+    AdjDesc descs[4][4];
+    for (int i = 0; i < nq; ++i) {
+        int base, sign, skip, ra, rb;
+        placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
+        for (int p = 0; p < gs[i].npass; ++p) {
+            AdjDesc& d = descs[i][p];
+            d = make_adj_desc(gs[i], p, S.grad, ld_hough, S.img, ld_img, w, h, S.ws, base, sign, skip,
+                              (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb, 0);
+            d.src_step = p == gs[i].npass - 1 ? S.grad_step : S.ws_step;
+            d.dst_step = p == 0 ? S.img_step : S.ws_step;
         }
-        for (int st = 1; st < n_steps; ++st) {
-            const int members[2] = {steps[st].u, steps[st].m};
-            for (int i : members) {
-                if (i < 0) continue;
-                descs[k][i][0].accumulate = 1;
-            }
-        }
+    }
+    for (int st = 1; st < n_steps; ++st) {
+        const int members[2] = {steps[st].u, steps[st].m};
+        for (int i : members)
+            if (i >= 0) descs[i][0].accumulate = 1;
     }
     int maxp = 0;
     for (int i = 0; i < nq; ++i) maxp = gs[i].npass > maxp ? gs[i].npass : maxp;
-    // band passes (p >= 1) in reverse order, every image's and quadrant's
-    // pass of one kind in one launch
+    // band passes (p >= 1) in reverse order, every quadrant's pass of one
+    // kind in one launch over the stack
     for (int p = maxp - 1; p >= 1; --p) {
         for (int G = 3; G <= kMaxG; ++G) {
             for (int first = 0; first < 2; ++first) {
                 AdjLaunch L{};
-                for (int k = 0; k < m; ++k)
-                    for (int i = 0; i < nq; ++i)
-                        if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first == 1))
-                            L.d[L.nd++] = descs[k][i][p];
+                L.n_img = S.m;
+                for (int i = 0; i < nq; ++i)
+                    if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G && (p == gs[i].npass - 1) == (first == 1))
+                        L.d[L.nd++] = descs[i][p];
                 if (L.nd == 0) continue;
                 hipError_t e = launch_adjoint_pass(L, t, s);
                 if (e != hipSuccess) return hip_fail(e, "adjoint pass launch");
@@ -1054,26 +1067,16 @@ int run_adjoint(const AdjImage* ims, int m, int t, int64_t ld_hough, int64_t ld_
     }
     // the image-pass steps, each once the previous one has stored
     for (int st = 0; st < n_steps; ++st) {
-        const Step& S = steps[st];
-        hipError_t e = hipSuccess;
-        if (S.m >= 0) {
-            AdjLaunch L{};
-            for (int k = 0; k < m; ++k) {
-                L.d[L.nd++] = descs[k][S.u][0];
-                L.d[L.nd++] = descs[k][S.m][0];
-            }
+        const Step& P = steps[st];
+        AdjLaunch L{};
+        L.n_img = S.m;
+        L.d[L.nd++] = descs[P.u][0];
+        hipError_t e;
+        if (P.m >= 0) {
+            L.d[L.nd++] = descs[P.m][0];
             e = launch_adjoint_pair(L, t, s);
-        } else if (gs[S.u].k > 2) {
-            AdjLaunch L{};
-            for (int k = 0; k < m; ++k) L.d[L.nd++] = descs[k][S.u][0];
-            e = launch_adjoint_pass(L, t, s);
         } else {
-            for (int k = 0; k < m && e == hipSuccess; ++k) {
-                AdjLaunch L{};
-                L.d[0] = descs[k][S.u][0];
-                L.nd = 1;
-                e = launch_adjoint_direct(L, gs[S.u].k, t, s);
-            }
+            e = gs[P.u].k > 2 ? launch_adjoint_pass(L, t, s) : launch_adjoint_direct(L, gs[P.u].k, t, s);
         }
         if (e != hipSuccess) return hip_fail(e, "adjoint image pass launch");
     }
@@ -1097,8 +1100,8 @@ int fht_adjoint(const void* grad_hough, int t, int64_t ld_hough, void* grad_img,
     if (need > 0 && (!workspace || ws_bytes < need))
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     if (workspace && ((uintptr_t)workspace & 255)) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
-    const AdjImage im{grad_hough, grad_img, (unsigned char*)workspace};
-    return run_adjoint(&im, 1, t, ld_hough, ld_img, w, h, quads, flags, (hipStream_t)stream);
+    const AdjStack S{grad_hough, grad_img, (unsigned char*)workspace, 0, 0, 0, 1};
+    return run_adjoint(S, t, ld_hough, ld_img, w, h, quads, flags, (hipStream_t)stream);
 }
 
 int fht_adjoint_stack_workspace_size(int w, int h, unsigned quads, int t, int n, size_t* bytes)
@@ -1108,7 +1111,8 @@ int fht_adjoint_stack_workspace_size(int w, int h, unsigned quads, int t, int n,
     size_t one = 0;
     int rc = fht_adjoint_workspace_size(w, h, quads, t, &one);
     if (rc) return rc;
-    *bytes = (size_t)(n < kStackGroup ? n : kStackGroup) * ((one + 255) / 256 * 256);
+    const size_t slice = (one + 255) / 256 * 256;
+    *bytes = (size_t)stack_group(slice, n) * slice;
     return FHT_OK;
 }
 
@@ -1131,17 +1135,21 @@ int fht_adjoint_stack(const void* grad_hough, int t, int64_t ld_hough, int64_t g
     if (!workspace || ws_bytes < need)
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
     if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
-    const size_t slice = need / (size_t)(n < kStackGroup ? n : kStackGroup);
+    size_t one = 0;
+    fht_adjoint_workspace_size(w, h, quads, t, &one);
+    const size_t slice = (one + 255) / 256 * 256;
+    const int group = stack_group(slice, n);
     const size_t esz = 4;
-    for (int i0 = 0; i0 < n; i0 += kStackGroup) {
-        const int m = n - i0 < kStackGroup ? n - i0 : kStackGroup;
-        AdjImage ims[kStackGroup];
-        for (int k = 0; k < m; ++k) {
-            ims[k].grad = (const unsigned char*)grad_hough + (size_t)(i0 + k) * (size_t)grad_stride * esz;
-            ims[k].img = (unsigned char*)grad_img + (size_t)(i0 + k) * (size_t)img_stride * esz;
-            ims[k].ws = (unsigned char*)workspace + (size_t)k * slice;
-        }
-        rc = run_adjoint(ims, m, t, ld_hough, ld_img, w, h, quads, flags, (hipStream_t)stream);
+    for (int i0 = 0; i0 < n; i0 += group) {
+        AdjStack S;
+        S.grad = (const unsigned char*)grad_hough + (size_t)i0 * (size_t)grad_stride * esz;
+        S.img = (unsigned char*)grad_img + (size_t)i0 * (size_t)img_stride * esz;
+        S.ws = (unsigned char*)workspace;
+        S.grad_step = grad_stride * (int64_t)esz;
+        S.img_step = img_stride * (int64_t)esz;
+        S.ws_step = (int64_t)slice;
+        S.m = n - i0 < group ? n - i0 : group;
+        rc = run_adjoint(S, t, ld_hough, ld_img, w, h, quads, flags, (hipStream_t)stream);
         if (rc) return rc;
     }
     return FHT_OK;

@@ -42,15 +42,17 @@ struct BatchTemplate {
 };
 
 // Copies the template table into the workspace with pointers resolved.
+// Image i is imgs[i], or with imgs == nullptr base + i * stride (bytes).
 __global__ void fht_batch_fixup_kernel(const EngineGroup* __restrict__ tmpl, const BatchTemplate* __restrict__ rel,
-                                       int n_groups, const void* const* imgs, unsigned char* hough,
-                                       unsigned char* ws, EngineGroup* out)
+                                       int n_groups, const void* const* imgs, const unsigned char* base,
+                                       int64_t stride, unsigned char* hough, unsigned char* ws, EngineGroup* out)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
     EngineGroup e = tmpl[g];
     const BatchTemplate r = rel[g];
-    e.d.src = r.src_is_ws ? (const void*)(ws + r.src_off) : imgs[r.img];
+    const void* img = imgs ? imgs[r.img] : (const void*)(base + (int64_t)r.img * stride);
+    e.d.src = r.src_is_ws ? (const void*)(ws + r.src_off) : img;
     e.d.dst = r.dst_is_ws ? (void*)(ws + r.dst_off) : (void*)(hough + r.dst_off);
     out[g] = e;
 }
@@ -228,10 +230,9 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
     return FHT_OK;
 }
 
-int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* hough, void* workspace, size_t ws_bytes,
-                      void* stream)
+static int batch_run(const fht_batch_plan* P, const void* const* imgs, const void* base, int64_t stride, void* hough,
+                     void* workspace, size_t ws_bytes, void* stream)
 {
-    if (!P || !imgs || !hough) return fail(FHT_ERR_INVALID, "null batch argument");
     if (!workspace || ws_bytes < P->ws_bytes)
         return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", P->ws_bytes,
                     workspace ? ws_bytes : 0);
@@ -239,7 +240,8 @@ int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* ho
     hipStream_t s = (hipStream_t)stream;
     EngineGroup* table = (EngineGroup*)workspace;
     hipLaunchKernelGGL(fht_batch_fixup_kernel, dim3((P->n_groups + 255) / 256), dim3(256), 0, s, P->d_tmpl, P->d_rel,
-                       P->n_groups, imgs, (unsigned char*)hough, (unsigned char*)workspace, table);
+                       P->n_groups, imgs, (const unsigned char*)base, stride, (unsigned char*)hough,
+                       (unsigned char*)workspace, table);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batch fixup launch");
     const int ti = P->in_t;
@@ -252,6 +254,27 @@ int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* ho
         if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }
     return FHT_OK;
+}
+
+int fht_batch_forward(const fht_batch_plan* P, const void* const* imgs, void* hough, void* workspace, size_t ws_bytes,
+                      void* stream)
+{
+    if (!P || !imgs || !hough) return fail(FHT_ERR_INVALID, "null batch argument");
+    return batch_run(P, imgs, nullptr, 0, hough, workspace, ws_bytes, stream);
+}
+
+int fht_batch_forward_stack(const fht_batch_plan* P, const void* base, int64_t stride_bytes, void* hough,
+                            void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!P || !base || !hough) return fail(FHT_ERR_INVALID, "null batch argument");
+    for (int i = 1; i < P->n; ++i)
+        if (P->ws[i] != P->ws[0] || P->hs[i] != P->hs[0])
+            return fail(FHT_ERR_INVALID, "a stack needs a plan of equal image sizes");
+    const int64_t bytes = (int64_t)P->ws[0] * P->hs[0] * (P->in_t == FHT_U8 ? 1 : 4);
+    if (P->n > 1 && stride_bytes < bytes)
+        return fail(FHT_ERR_INVALID, "stride %lld bytes < one image (%lld bytes)", (long long)stride_bytes,
+                    (long long)bytes);
+    return batch_run(P, nullptr, base, stride_bytes, hough, workspace, ws_bytes, stream);
 }
 
 int fht_batch_plan_destroy(fht_batch_plan* P)

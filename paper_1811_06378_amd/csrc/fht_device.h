@@ -1007,6 +1007,15 @@ __device__ __forceinline__ void adj_exchange(T (&b)[8][8], T (&a)[8][8], T* lds,
     }
 }
 
+// A private copy of descriptor k of a launch, for stack image im.
+__device__ __forceinline__ AdjDesc adj_desc_for(const AdjLaunch& L, int k, int im)
+{
+    AdjDesc d = L.d[k];
+    d.src = reinterpret_cast<const unsigned char*>(d.src) + (int64_t)im * d.src_step;
+    d.dst = reinterpret_cast<unsigned char*>(d.dst) + (int64_t)im * d.dst_step;
+    return d;
+}
+
 // One adjoint tile up to its stores: the forward pass's output rows of row
 // tile rt at the window whose first own column is xi = x_lo (8 waves, wave
 // 0..7 of them, exchange in lds), through the exchange and the stages, into
@@ -1193,7 +1202,9 @@ template <typename T, int GB, bool FIRST, bool LAST, bool ACC>
 __global__ __launch_bounds__(kThreads, 4) void fht_adj_pass_kernel(const AdjLaunch L)
 {
     __shared__ T lds[kTileRows / 2 * kLdsRow];
-    const AdjDesc d = L.d[blockIdx.z];  // a private copy: its fields stay in registers across the stores
+    // a private copy: its fields stay in registers across the stores
+    const int k = uniform((int)blockIdx.z % L.nd);
+    const AdjDesc d = adj_desc_for(L, k, uniform((int)blockIdx.z / L.nd));
     if ((int)blockIdx.x >= d.n_windows || (int)blockIdx.y >= d.n_row_tiles) return;
     adj_tile<T, GB, FIRST, LAST, ACC>(d, blockIdx.y, blockIdx.x, lds);
 }
@@ -1218,13 +1229,15 @@ __global__ __launch_bounds__(2 * kThreads, 4) void fht_adj_pair_kernel(const Adj
     constexpr int nmini_tile = 1 << (6 - G);
     constexpr int kCbRow = kWinCols;  // combine buffer: one row per tile row
     static_assert(kTileRows * kCbRow <= kTileRows * kLdsRow, "combine buffer exceeds the exchange regions");
-    // the whole workgroup leaves together (U's counts bound the pair)
-    if ((int)blockIdx.x >= L.d[2 * blockIdx.z].n_windows || (int)blockIdx.y >= L.d[2 * blockIdx.z].n_row_tiles)
-        return;
+    // pair p of stack image im: z = im * (nd / 2) + p; the whole workgroup
+    // leaves together (U's counts bound the pair)
+    const int np = L.nd >> 1;
+    const int pz = uniform((int)blockIdx.z % np);
+    if ((int)blockIdx.x >= L.d[2 * pz].n_windows || (int)blockIdx.y >= L.d[2 * pz].n_row_tiles) return;
     const int half = uniform((int)threadIdx.x >> 9);
     const int wave = uniform(((int)threadIdx.x >> 6) & 7);
     const int lane = threadIdx.x & 63;
-    const AdjDesc d = L.d[2 * blockIdx.z + half];
+    const AdjDesc d = adj_desc_for(L, 2 * pz + half, uniform((int)blockIdx.z / np));
     const int c0 = blockIdx.x * VW;
     const int x_lo = half == 0 ? c0 : d.W - c0 - VW + 1;
     T a[8][8];
@@ -1417,7 +1430,7 @@ __device__ T adj_direct(const AdjDesc& d, int row, int x)
 template <typename T, int K>
 __global__ __launch_bounds__(256) void fht_adj_direct_kernel(const AdjLaunch L)
 {
-    const AdjDesc& d = L.d[blockIdx.z];
+    const AdjDesc d = adj_desc_for(L, (int)blockIdx.z % L.nd, (int)blockIdx.z / L.nd);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int R = blockIdx.y;
     if (R >= d.n) return;

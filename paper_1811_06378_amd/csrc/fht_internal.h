@@ -88,12 +88,17 @@ struct AdjDesc {
     int shifted, roll_a, roll_b;
     int black_lo;         // Hough source: xi in [black_lo, black_lo + n - s) of row s is
     int black_ok;         // the structurally zero zone; 1: read it as zero (no shear)
+    int64_t src_step;     // bytes from one stack image's source to the next's
+    int64_t dst_step;     // bytes from one stack image's destination to the next's
 };
-// Up to 4 images x 4 quadrants of one adjoint pass kind in one launch.
-constexpr int kMaxAdjDescs = 16;
+// Up to 4 quadrants' descriptors of one adjoint pass kind, for n_img images
+// of a stack: launch z = image * nd + descriptor, and image i's descriptors
+// have src and dst advanced by i * src_step and i * dst_step.
+constexpr int kMaxAdjDescs = 4;
 struct AdjLaunch {
     AdjDesc d[kMaxAdjDescs];
     int nd;
+    int n_img;  // < 1 counts as 1
 };
 
 // Persistent forward engine: an ordered queue of items (one tile each) drawn

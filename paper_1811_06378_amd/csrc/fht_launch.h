@@ -159,7 +159,7 @@ hipError_t launch_adj_pass_g(const AdjLaunch& L, hipStream_t s)
         ry = L.d[i].n_row_tiles > ry ? L.d[i].n_row_tiles : ry;
     }
     const bool first = L.d[0].src_kind == 0, last = L.d[0].dst_kind != 0;
-    const dim3 grid(wx, ry, L.nd);
+    const dim3 grid(wx, ry, L.nd * (L.n_img > 0 ? L.n_img : 1));
     // image passes that add to the stored gradient run their own instantiation; all
     // descriptors of a launch agree
     const bool acc = last && L.d[0].accumulate != 0;
@@ -215,7 +215,7 @@ hipError_t launch_adj_pair_g(const AdjLaunch& L, hipStream_t s)
         ry = u.n_row_tiles > ry ? u.n_row_tiles : ry;
     }
     const bool first = L.d[0].src_kind == 0, acc = L.d[0].accumulate != 0;
-    const dim3 grid(wx, ry, L.nd / 2), block(2 * kThreads);
+    const dim3 grid(wx, ry, (L.nd / 2) * (L.n_img > 0 ? L.n_img : 1)), block(2 * kThreads);
     if (first && acc) hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, true, true>), grid, block, 0, s, L);
     else if (first) hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, true, false>), grid, block, 0, s, L);
     else if (acc) hipLaunchKernelGGL((fht_adj_pair_kernel<T, GB, false, true>), grid, block, 0, s, L);
@@ -244,7 +244,7 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
         cols = c > cols ? c : cols;
         n = L.d[i].n > n ? L.d[i].n : n;
     }
-    const dim3 grid((cols + 255) / 256, n, L.nd);
+    const dim3 grid((cols + 255) / 256, n, L.nd * (L.n_img > 0 ? L.n_img : 1));
     switch (k) {
     case 0: hipLaunchKernelGGL((fht_adj_direct_kernel<T, 0>), grid, dim3(256), 0, s, L); break;
     case 1: hipLaunchKernelGGL((fht_adj_direct_kernel<T, 1>), grid, dim3(256), 0, s, L); break;

@@ -85,6 +85,7 @@ int main()
     EXPECT(fht_batch_plan_create(ws1, hs1, 0, FHT_FULL, FHT_U8, FHT_I32, &plan, &b, &tot, nullptr) < 0);
     EXPECT(fht_batch_plan_create(nullptr, hs1, 1, FHT_FULL, FHT_U8, FHT_I32, &plan, &b, &tot, nullptr) < 0);
     EXPECT(fht_batch_forward(nullptr, nullptr, p, p, 1u << 30, nullptr) < 0);
+    EXPECT(fht_batch_forward_stack(nullptr, p, 64, p, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_batch_plan_destroy(nullptr) == FHT_OK);
     for (int st = -6; st <= 0; ++st) EXPECT(fht_status_string(st) != nullptr);
     EXPECT(fht_last_error() != nullptr);

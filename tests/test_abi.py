@@ -42,7 +42,13 @@ def test_adjoint_stack_sizes_and_validation():
     one256 = (one + 255) // 256 * 256
     assert fht.adjoint_stack_workspace_size(300, 200, 1) == one256
     assert fht.adjoint_stack_workspace_size(300, 200, 3) == 3 * one256
-    assert fht.adjoint_stack_workspace_size(300, 200, 100) == 4 * one256  # groups of 4
+    assert fht.adjoint_stack_workspace_size(300, 200, 100) == 100 * one256  # one group
+    # groups keep their bands within 2 GiB: 4096^2 images (275 MB of bands each) run 7 at a time
+    big = (fht.adjoint_workspace_size(4096, 4096) + 255) // 256 * 256
+    per_group = (2 << 30) // big
+    assert 1 <= per_group < 16
+    assert fht.adjoint_stack_workspace_size(4096, 4096, 16) == per_group * big
+    assert fht.adjoint_stack_workspace_size(4096, 4096, 1) == big
     rows, cols = fht.hough_shape(300, 200)
     p = ctypes.c_void_p(1 << 20)
     args = dict(t=fht.FHT_F32, ld=cols, gs=rows * cols, ldi=300, istr=300 * 200, n=3)

@@ -56,8 +56,8 @@ def test_batch_forward_reuses_plan_with_new_data():
 @pytest.mark.parametrize("streams", [1, 2, 3])
 @pytest.mark.parametrize("n", [1, 3, 4, 5, 9])
 def test_batch_adjoint_equals_single(n, streams):
-    # groups of up to 4 images per launch: 9 = 4 + 4 + 1; with streams > 1
-    # the stack is split over side streams once it has 2 images per stream
+    # one launch per pass kind over the stack; with streams > 1 the stack is
+    # split over side streams once it has 2 images per stream
     h, w = 120, 75
     rows, cols = fht.hough_shape(w, h)
     rng = np.random.default_rng(n * 10 + streams)
@@ -68,6 +68,24 @@ def test_batch_adjoint_equals_single(n, streams):
         assert torch.equal(got[i], P.adjoint(g[i], w, h))
     np.testing.assert_allclose(host(got[0]).astype(np.float64),
                                oracle.adjoint_full(host(g[0]).astype(np.float64), w, h), rtol=1e-4, atol=1e-3)
+
+
+def test_batch_adjoint_groups_of_large_images():
+    """4096^2 gradients: a group holds as many images as keep their bands
+    within 2 GiB (7), so 9 images run as groups of 7 and 2 reusing one
+    workspace; every image equals the single-image adjoint bit for bit."""
+    h = w = 4096
+    rows, cols = fht.hough_shape(w, h)
+    n = 9
+    one = (fht.adjoint_workspace_size(w, h) + 255) // 256 * 256
+    assert fht.adjoint_stack_workspace_size(w, h, n) == ((2 << 30) // one) * one < n * one
+    g = torch.empty((n, rows, cols), device="cuda").normal_(generator=torch.Generator(device="cuda").manual_seed(9))
+    got = P.batch_adjoint(g, w, h)
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert torch.equal(got[i], P.adjoint(g[i], w, h)), "image %d" % i
+    del g, got
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("quads,shifted", [([2, 3], False), ([1], False), ("full", True)])

@@ -121,3 +121,68 @@ def test_batch_graph_replay():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(packed, eager), "replay %d differs" % rep
+
+
+@pytest.mark.parametrize("kind,n,h,w", [("u8", 5, 100, 37), ("f32", 3, 129, 64), ("i32", 4, 3, 70), ("f32", 1, 1, 1)])
+def test_stack_entry_matches_oracle_and_pointer_table(kind, n, h, w):
+    """fht_batch_forward_stack (image i at base + i * stride, resolved on the
+    device): every image bit-exact against the oracle and identical to the
+    pointer-table call, into poisoned outputs and workspaces; a stride larger
+    than one image (a sliced stack) works the same."""
+    dt = {"u8": torch.uint8, "i32": torch.int32, "f32": torch.float32}[kind]
+    imgs = [synth.random_image(h, w, kind, seed=70 + i) for i in range(n)]
+    plan = fht.BatchPlan([(h, w)] * n, in_dtype=dt)
+    x = torch.stack([dev(a) for a in imgs])
+    packed = P.poisoned((plan.out_elems,), plan.out_dtype)
+    plan.run_stack(x, packed, workspace=P.poisoned_ws(plan.workspace_bytes))
+    ref = P.batch_run(plan, [x[i] for i in range(n)])
+    for i, (a, v) in enumerate(zip(imgs, plan.views(packed))):
+        assert torch.equal(v, ref[i]), "stack image %d differs from the pointer-table call" % i
+        want = oracle.full(a.astype(np.float64), single=(kind == "f32"))
+        assert_equal(host(v).astype(np.float64), want, "stack %s image %d" % (kind, i))
+    # every other image of a 2n stack: stride of two images
+    big = torch.stack([x[i // 2] for i in range(2 * n)])[::2]
+    assert big.stride(0) == 2 * h * w
+    packed2 = P.poisoned((plan.out_elems,), plan.out_dtype)
+    rc = fht.lib().fht_batch_forward_stack(plan._plan, big.data_ptr(), big.stride(0) * big.element_size(),
+                                           packed2.data_ptr(), plan.workspace.data_ptr(), plan.workspace.numel(),
+                                           fht._stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(packed2, packed)
+
+
+def test_stack_entry_graph_replay_and_rejections():
+    n, h, w = 6, 300, 200
+    x = torch.stack([dev(synth.random_image(h, w, "f32", seed=80 + i)) for i in range(n)])
+    plan = fht.BatchPlan([(h, w)] * n, in_dtype=torch.float32)
+    eager = plan.output()
+    plan.run_stack(x, eager)
+    torch.cuda.synchronize()
+    packed = plan.output()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run_stack(x, packed)
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        plan.run_stack(x, packed)
+    for rep in range(3):
+        packed.fill_(-1.0)
+        _ = torch.randn(1000, device="cuda").sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(packed, eager), "replay %d differs" % rep
+    del g
+    L = fht.lib()
+    ws = plan.workspace
+    # a stride shorter than one image, and a plan of unequal sizes, are rejected before any launch
+    assert L.fht_batch_forward_stack(plan._plan, x.data_ptr(), h * w * 4 - 4, packed.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), fht._stream()) == fht.FHT_ERR_INVALID
+    mixed = fht.BatchPlan([(h, w), (h, w + 1)], in_dtype=torch.float32)
+    out = mixed.output()
+    assert L.fht_batch_forward_stack(mixed._plan, x.data_ptr(), h * w * 4, out.data_ptr(), mixed.workspace.data_ptr(),
+                                     mixed.workspace.numel(), fht._stream()) == fht.FHT_ERR_INVALID
+    with pytest.raises(ValueError):
+        mixed.run_stack(x[:2], out)
