@@ -157,6 +157,46 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+def bench_stack(fht, torch, x, steps, warmup, label):
+    """Stack forward (fht_forward_stack, captured once in a HIP graph and
+    replayed) and the same images through single-image forwards, into the
+    same output."""
+    n, h, w = x.shape
+    rows, cols = fht.hough_shape(w, h)
+    out = torch.empty((n, rows, cols), dtype=torch.float32 if x.dtype == torch.float32 else torch.int32, device="cuda")
+    ws = torch.empty(max(fht.forward_stack_workspace_size(w, h, n, "full", x.dtype), 256), dtype=torch.uint8,
+                     device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fht.batch_forward(x, out=out, workspace=ws)  # warm-up outside the graph
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(graph):
+        fht.batch_forward(x, out=out, workspace=ws)
+    ms_stack = _timed(graph.replay, steps, warmup, torch)
+    ws1 = torch.empty(max(fht.workspace_size(w, h, "full", x.dtype), 256), dtype=torch.uint8, device="cuda")
+
+    def loop():
+        for i in range(n):
+            fht.forward(x[i], out=out[i], workspace=ws1)
+
+    ms_loop = _timed(loop, steps, warmup, torch)
+    px = n * h * w
+    out_bytes = out.numel() * out.element_size()
+    in_bytes = x.numel() * x.element_size()
+    res = {"value": round(px / (ms_stack * 1e-3) / 1e9, 3), "unit": "Gpixels/s", "ms_per_step": round(ms_stack, 4),
+           "images": n, "pixels": px, "hough_cells": out.numel(),
+           "hbm_compulsory_frac": round((in_bytes + out_bytes) / (ms_stack * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "single_image_loop": {"value": round(px / (ms_loop * 1e-3) / 1e9, 3), "ms_per_step": round(ms_loop, 4)},
+           "launch": "fht_forward_stack (one launch per pass kind over the stack), captured in a HIP graph and "
+                     "replayed"}
+    log("%s: stacked %.3f ms, single-image loop %.3f ms" % (label, ms_stack, ms_loop))
+    del graph, out, ws, ws1
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batch(fht, torch, imgs, steps, warmup, label):
     """Batched forward (captured once in a HIP graph, replayed) and the same
     images through single-image forwards, into the same packed output."""
@@ -481,9 +521,13 @@ def main():
         log("fwd+adjoint %.3f ms" % ms_fa)
 
         imgs8 = [x] + [torch.from_numpy(synth.dense4096(s, size=side)).cuda() for s in range(1, 8)]
-        result["batched"] = bench_batch(fht, torch, imgs8, max(1, args.steps // 4), 1, "batched 8x4096^2 f32")
-        result["batched"]["workload"] = "8 dense4096 images (seeds 0..7), float32"
-        del imgs8
+        x8 = torch.stack(imgs8)
+        result["batched"] = bench_stack(fht, torch, x8, max(1, args.steps // 4), 1, "batched 8x4096^2 f32")
+        result["batched"]["workload"] = "8 dense4096 images (seeds 0..7), float32, one (8, 4096, 4096) stack"
+        plan_line = bench_batch(fht, torch, imgs8, max(1, args.steps // 4), 1, "batch plan 8x4096^2 f32")
+        result["batched"]["batch_plan"] = {"value": plan_line["value"], "ms_per_step": plan_line["ms_per_step"],
+                                           "launch": plan_line["launch"]}
+        del imgs8, x8
 
         result["sparse1024"] = bench_sparse1024(fht, synth, torch, max(5, args.steps))
         result["diff16x1024"] = bench_diff16(fht, synth, torch, max(5, args.steps // 2))
@@ -503,7 +547,7 @@ def main():
             fht, ks, lambda: batch_graph_ms(fht, torch, imgs512, 3, packed=packed))
         del packed
         torch.cuda.empty_cache()
-        result["batch512"] = bench_batch(fht, torch, imgs512, 3, 1, "batch512 u8")
+        result["batch512"] = bench_batch(fht, torch, imgs512, 6, 2, "batch512 u8")
         result["batch512"]["workload"] = "512 uint8 images, sides uniform in 64..2048 (seed 0), int32 Hough images"
         result["batch512"]["tuning"] = {"default": default, "default_ms": round(ms_default, 3), "used": chosen,
                                         "tuned_ms": round(ms_tuned, 3),

@@ -126,6 +126,21 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
                 size_t ws_bytes, void* stream);
 
 /*
+ * fht_forward of a stack of n same-size images in one set of launches (the
+ * image index runs on the launch grid): image i at img + i * img_stride
+ * elements (img_stride >= h * ld_img when n > 1), its Hough image at
+ * hough + i * hough_stride elements (hough_stride >= rows * ld_hough when
+ * n > 1).  Every other argument as fht_forward; results equal n calls of
+ * fht_forward bit for bit.  Images run in groups whose bands fit 8 GiB; the
+ * workspace (>= fht_forward_stack_workspace_size, 256-byte aligned) holds
+ * one single-image workspace (rounded up to 256 bytes) per image of a group.
+ */
+int fht_forward_stack_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, int n, size_t* bytes);
+int fht_forward_stack(const void* img, int in_t, int w, int h, int64_t ld_img, int64_t img_stride, int n,
+                      void* hough, int acc_t, int64_t ld_hough, int64_t hough_stride, unsigned quads,
+                      unsigned flags, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Allocation-free forward, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, results and errors as fht_forward, without

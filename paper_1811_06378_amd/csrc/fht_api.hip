@@ -410,8 +410,10 @@ static bool use_engine()
 
 // Runs the forward passes of the quadrant geometries gs[0..nq).
 // op: 0 = sum along the patterns, 1 = max.
+// m > 1: a stack of m images, the descriptors' steps giving image i's
+// buffers; every launch covers all m (never the engine).
 static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, int in_t, int acc_t, unsigned* sync,
-                       hipStream_t stream, int op = 0)
+                       hipStream_t stream, int op = 0, int m = 1)
 {
     // quadrants with at most two stages: one direct launch
     for (int i = 0; i < nq; ++i) {
@@ -419,6 +421,7 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
         PassLaunch L{};
         L.d[0] = descs[i][0];
         L.nd = 1;
+        L.n_img = m;
         hipError_t e = launch_direct(L, gs[i].k, in_t, acc_t, stream, op);
         if (e != hipSuccess) return hip_fail(e, "direct launch");
     }
@@ -426,7 +429,7 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
     for (int i = 0; i < nq; ++i) sheared |= descs[i][0].S1 != 0 || descs[i][0].scale_num != 0;
     // the engine runs unsheared, unscaled sources only; the angle range
     // always takes the per-pass launches
-    if (use_engine() && op == 0 && !sheared) {
+    if (use_engine() && op == 0 && !sheared && m == 1) {
         std::vector<EngineGroup> groups;
         const int total = append_engine_groups(gs, descs, nq, groups, 0);
         return run_engine(groups, nullptr, total, sync, in_t, acc_t, stream);
@@ -438,6 +441,7 @@ static int run_forward(const QuadGeom* gs, const PassDesc (*descs)[4], int nq, i
             for (int last = 0; last < 2; ++last) {
                 for (int rows = kTileRows; rows >= kNarrowRows; rows /= 2) {
                     PassLaunch L{};
+                    L.n_img = m;
                     for (int i = 0; i < nq; ++i)
                         if (gs[i].k > 2 && p < gs[i].npass && gs[i].G[p] == G &&
                             (p == gs[i].npass - 1) == (last == 1) && descs[i][p].tile_rows == rows)
@@ -780,6 +784,79 @@ int fht_forward(const void* img, int in_t, int w, int h, int64_t ld_img, void* h
     }
     return run_forward(gs, descs, nq, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream,
                        (flags & FHT_FLAG_MAX) ? 1 : 0);
+}
+
+// Images of a forward stack per group: their bands within 8 GiB (the batch
+// plan's chunk), at most 65535 (the launch grid's y extent).
+static int forward_stack_group(size_t slice, int n)
+{
+    const size_t budget = size_t(8) << 30;
+    size_t g = slice ? budget / slice : (size_t)n;
+    if (g > 65535) g = 65535;
+    if (g > (size_t)n) g = (size_t)n;
+    return g < 1 ? 1 : (int)g;
+}
+
+int fht_forward_stack_workspace_size(int w, int h, unsigned quads, int in_t, int acc_t, int n, size_t* bytes)
+{
+    if (!bytes) return fail(FHT_ERR_INVALID, "null bytes output");
+    if (n < 1) return fail(FHT_ERR_INVALID, "stack of %d images", n);
+    size_t one = 0;
+    int rc = fht_workspace_size(w, h, quads, in_t, acc_t, &one);
+    if (rc) return rc;
+    const size_t slice = (one + 255) / 256 * 256;
+    *bytes = (size_t)forward_stack_group(slice, n) * slice;
+    return FHT_OK;
+}
+
+int fht_forward_stack(const void* img, int in_t, int w, int h, int64_t ld_img, int64_t img_stride, int n, void* hough,
+                      int acc_t, int64_t ld_hough, int64_t hough_stride, unsigned quads, unsigned flags,
+                      void* workspace, size_t ws_bytes, void* stream)
+{
+    size_t one = 0;
+    int rc = forward_check(img, in_t, w, h, ld_img, hough, acc_t, ld_hough, quads, flags, &one);
+    if (rc) return rc;
+    if (n < 1) return fail(FHT_ERR_INVALID, "stack of %d images", n);
+    int64_t rows, cols;
+    fht_hough_shape(w, h, quads, &rows, &cols);
+    if (n > 1 && img_stride < (int64_t)h * ld_img)
+        return fail(FHT_ERR_INVALID, "img_stride %lld < h * ld_img", (long long)img_stride);
+    if (n > 1 && hough_stride < rows * ld_hough)
+        return fail(FHT_ERR_INVALID, "hough_stride %lld < rows * ld_hough", (long long)hough_stride);
+    const size_t slice = (one + 255) / 256 * 256;
+    const int group = forward_stack_group(slice, n);
+    const size_t need = (size_t)group * slice;
+    if (!workspace || ws_bytes < need)
+        return fail(FHT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
+    if ((uintptr_t)workspace & 255) return fail(FHT_ERR_INVALID, "workspace must be 256-byte aligned");
+    int qs[4];
+    const int nq = selected_quads(quads, qs);
+    QuadGeom gs[4];
+    for (int i = 0; i < nq; ++i) gs[i] = quad_geom(w, h, qs[i], 0);
+    forward_workspace(gs, nq, acc_t);  // lays out the bands in gs
+    const int64_t img_step = img_stride * (int64_t)elem_size(in_t);
+    const int64_t hough_step = hough_stride * (int64_t)elem_size(acc_t);
+    for (int i0 = 0; i0 < n; i0 += group) {
+        const int m = n - i0 < group ? n - i0 : group;
+        const unsigned char* im0 = (const unsigned char*)img + (int64_t)i0 * img_step;
+        unsigned char* h0 = (unsigned char*)hough + (int64_t)i0 * hough_step;
+        PassDesc descs[4][4];
+        for (int i = 0; i < nq; ++i) {
+            int base, sign, skip, ra, rb;
+            placement(w, h, quads, qs[i], &base, &sign, &skip, &ra, &rb);
+            for (int p = 0; p < gs[i].npass; ++p) {
+                PassDesc& d = descs[i][p];
+                d = make_pass_desc(gs[i], p, im0, w, h, ld_img, h0, ld_hough, (unsigned char*)workspace, 0, INT_MAX,
+                                   base, sign, skip, (flags & FHT_FLAG_SHIFTED) ? 1 : 0, ra, rb);
+                d.src_step = p == 0 ? img_step : (int64_t)slice;
+                d.dst_step = p == gs[i].npass - 1 ? hough_step : (int64_t)slice;
+            }
+        }
+        rc = run_forward(gs, descs, nq, in_t, acc_t, (unsigned*)workspace, (hipStream_t)stream,
+                         (flags & FHT_FLAG_MAX) ? 1 : 0, m);
+        if (rc) return rc;
+    }
+    return FHT_OK;
 }
 
 int fht_range(const void* img, int in_t, int w, int h, int64_t ld_img, int S1, int S, int transposed, void* hough,

@@ -772,8 +772,11 @@ __global__ __launch_bounds__(NW * 64, 4) void fht_pass_kernel(const PassLaunch L
         ++z;
     }
     // a private copy of the descriptor: a reference into the arguments at a
-    // dynamic index had every stored row read its fields again
-    const PassDesc d = L.d[z];
+    // dynamic index had every stored row read its fields again; stack image
+    // blockIdx.y reads and writes its own buffers
+    PassDesc d = L.d[z];
+    d.src = reinterpret_cast<const unsigned char*>(d.src) + (int64_t)blockIdx.y * d.src_step;
+    d.dst = reinterpret_cast<unsigned char*>(d.dst) + (int64_t)blockIdx.y * d.dst_step;
     const int rt = t / d.n_windows;
     fwd_tile<TIn, T, GB, FIRST, LAST, OP, NW, SRCM>(d, rt, t - rt * d.n_windows, lds);
 }
@@ -1364,7 +1367,11 @@ __device__ T direct_sum(const PassDesc& d, int base, int s, int x)
 template <typename TIn, typename T, int K, int OP>
 __global__ __launch_bounds__(256) void fht_direct_kernel(const PassLaunch L)
 {
-    const PassDesc& d = L.d[blockIdx.z];
+    // z = stack image * nd + descriptor
+    PassDesc d = L.d[(int)blockIdx.z % L.nd];
+    const int64_t im = (int)blockIdx.z / L.nd;
+    d.src = reinterpret_cast<const unsigned char*>(d.src) + im * d.src_step;
+    d.dst = reinterpret_cast<unsigned char*>(d.dst) + im * d.dst_step;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (x >= d.W || s >= d.n || s > d.row_limit || s == d.skip_row) return;

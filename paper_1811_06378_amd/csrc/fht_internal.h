@@ -60,13 +60,19 @@ struct PassDesc {
     int scale_num, scale_den;  // first pass: source sample floor(x * den / num) along the
                                // sheared axis (section 4 scale); 0 = no scaling
     int tile_rows;        // 64 (8 waves) or 32 (4 waves, G <= 5); n_row_tiles = ceil(n / tile_rows)
+    int64_t src_step;     // bytes from one stack image's source to the next's (pass launches)
+    int64_t dst_step;     // bytes from one stack image's destination to the next's
 };
 
+// Up to 4 quadrants' descriptors of one pass kind, for n_img images of a
+// stack: image i (grid y; z for the direct kernel) has every descriptor's
+// src and dst advanced by i * src_step and i * dst_step.
 constexpr int kMaxDescs = 4;
 struct PassLaunch {
     PassDesc d[kMaxDescs];
     int nd;
     int n_tiles;  // sum of n_row_tiles * n_windows (filled by the launcher)
+    int n_img;    // < 1 counts as 1
 };
 
 // Adjoint pass: the transpose of one forward pass, in the same xi coordinate.

@@ -15,7 +15,7 @@ hipError_t launch_pass_g(const PassLaunch& L0, hipStream_t s)
     for (int i = 0; i < L.nd; ++i) L.n_tiles += L.d[i].n_row_tiles * L.d[i].n_windows;
     if (L.n_tiles == 0) return hipSuccess;
     const bool first = L.d[0].src_kind != SRC_BAND, last = L.d[0].dst_kind == DST_HOUGH;
-    const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds), block(NW * 64);
+    const dim3 grid((L.n_tiles + kXcds - 1) / kXcds * kXcds, L.n_img > 0 ? L.n_img : 1), block(NW * 64);
     // first passes of sheared or scaled sources (angle range, sum only) take
     // the kernel with their source path; every descriptor of a launch agrees
     int mode = 0;
@@ -140,7 +140,7 @@ hipError_t launch_direct_t(const PassLaunch& L, int k, hipStream_t s)
         W = L.d[i].W > W ? L.d[i].W : W;
         n = L.d[i].n > n ? L.d[i].n : n;
     }
-    const dim3 grid((W + 255) / 256, n, L.nd);
+    const dim3 grid((W + 255) / 256, n, L.nd * (L.n_img > 0 ? L.n_img : 1));
     switch (k) {
     case 0: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 0, OP>), grid, dim3(256), 0, s, L); break;
     case 1: hipLaunchKernelGGL((fht_direct_kernel<TIn, T, 1, OP>), grid, dim3(256), 0, s, L); break;

@@ -60,6 +60,8 @@ SIGNATURES = {
     "fht_adjoint_workspace_size": (_I, [_I, _I, _U, _I, _PSZ]),
     "fht_forward": (_I, [_P, _I, _I, _I, _I64, _P, _I, _I64, _U, _U, _P, _SZ, _P]),
     "fht_forward_noalloc": (_I, [_P, _I, _I, _I, _I64, _P, _I, _I64, _U, _U, _P]),
+    "fht_forward_stack_workspace_size": (_I, [_I, _I, _U, _I, _I, _I, _PSZ]),
+    "fht_forward_stack": (_I, [_P, _I, _I, _I, _I64, _I64, _I, _P, _I, _I64, _I64, _U, _U, _P, _SZ, _P]),
     "fht_range": (_I, [_P, _I, _I, _I, _I64, _I, _I, _I, _P, _I, _I64, _P, _SZ, _P]),
     "fht_shift": (_I, [_P, _I64, _P, _I64, _I, _I, _I, _I, _P]),
     "fht_adjoint": (_I, [_P, _I, _I64, _P, _I64, _I, _I, _U, _U, _P, _SZ, _P]),
@@ -210,9 +212,8 @@ def pass_split(side: int):
 
 
 def set_pass_split(k: int, passes=None):
-    """Stage split for quadrants of 2^k rows (None restores the default).
-    Cached stack plans are dropped, so later stacks are planned with it."""
-    _plan_cache.clear()
+    """Stage split for quadrants of 2^k rows (None restores the default);
+    calls and batch plans created from now on use it."""
     if passes is None:
         _check(lib().fht_set_pass_split(k, 0, None), "fht_set_pass_split")
         return
@@ -222,9 +223,8 @@ def set_pass_split(k: int, passes=None):
 
 def set_tile_rows(k: int, rows: int | None = None):
     """Tile height (32 or 64) for passes of at most 5 stages of quadrants
-    with 2^k rows (None restores the default rule).  Cached stack plans are
-    dropped."""
-    _plan_cache.clear()
+    with 2^k rows (None restores the default rule); calls and batch plans
+    created from now on use it."""
     _check(lib().fht_set_tile_rows(k, 0 if rows is None else int(rows)), "fht_set_tile_rows")
 
 
@@ -240,7 +240,6 @@ def autotune(w: int, h: int, in_dtype=torch.float32, reps: int = 20):
     now used for both sides."""
     it, at, _ = _dtypes(in_dtype)
     _check(lib().fht_autotune(w, h, it, at, reps, _stream()), "fht_autotune")
-    _plan_cache.clear()
     return pass_split(h), pass_split(w)
 
 
@@ -557,7 +556,6 @@ class FHTFunction(torch.autograd.Function):
         return batch_adjoint(g, w, h, ctx.quads, ctx.shifted, streams=BACKWARD_STREAMS), None, None
 
 
-_plan_cache = {}
 # side streams for the backward of an image stack (1: the caller's stream).
 # One adjoint launch per pass kind already covers the whole stack, so side
 # streams add host work and no overlap (16 x 1024^2: 325 us on one stream,
@@ -565,34 +563,46 @@ _plan_cache = {}
 BACKWARD_STREAMS = 1
 
 
-def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False) -> torch.Tensor:
+def forward_stack_workspace_size(w: int, h: int, n: int, quads="full", in_dtype=torch.float32) -> int:
+    it, at, _ = _dtypes(in_dtype)
+    b = ctypes.c_size_t()
+    _check(lib().fht_forward_stack_workspace_size(w, h, _quads(quads), it, at, n, ctypes.byref(b)),
+           "fht_forward_stack_workspace_size")
+    return b.value
+
+
+def batch_forward(x: torch.Tensor, quads="full", shifted: bool = False, out: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None, op: str = "sum") -> torch.Tensor:
     """Hough images of a (batch, h, w) stack of same-size images, into one
-    (batch, rows, cols) tensor.  Without fhtshift this is
-    one batch plan (one launch per pass class for the whole stack, cached per
-    shape); otherwise one forward per image, each written in place."""
+    (batch, rows, cols) tensor (fht_forward_stack: one launch per pass kind
+    over the stack, in groups whose bands fit 8 GiB)."""
+    if op not in ("sum", "max"):
+        raise ValueError("op must be 'sum' or 'max'")
     if x.dim() != 3:
         raise ValueError("batch_forward takes a (batch, h, w) tensor")
-    x = x.contiguous()
+    if x.stride(2) != 1 or x.stride(1) < x.shape[2] or x.stride(0) < x.shape[1] * x.stride(1):
+        x = x.contiguous()
     n, h, w = x.shape
+    it, at, odt = _dtypes(x.dtype)
     q = _quads(quads)
     rows, cols = hough_shape(w, h, q)
-    _, _, odt = _dtypes(x.dtype)
-    out = torch.empty((n, rows, cols), dtype=odt, device=x.device)
+    if out is None:
+        out = torch.empty((n, rows, cols), dtype=odt, device=x.device)
+    elif (out.dim() != 3 or tuple(out.shape) != (n, rows, cols) or out.dtype != odt or out.stride(2) != 1
+          or (rows > 1 and out.stride(1) < cols) or (n > 1 and out.stride(0) < rows * out.stride(1))):
+        raise ValueError("out must be a (%d, %d, %d) %s tensor with unit column stride" % (n, rows, cols, odt))
     if n == 0:
         return out
-    if shifted or n == 1:
-        for i in range(n):
-            forward(x[i], q, shifted, out=out[i])
-        return out
-    key = (n, h, w, q, x.dtype, x.device)
-    plan = _plan_cache.get(key)
-    if plan is None:
-        plan = BatchPlan([(h, w)] * n, q, x.dtype, x.device)
-        if plan.offsets != [i * rows * cols for i in range(n)]:
-            raise RuntimeError("batch plan does not lay out equal images back to back")
-        _plan_cache[key] = plan
-    ws = _workspace(plan.workspace_bytes, x.device)
-    plan.run_stack(x, out.view(-1), workspace=ws)
+    need = forward_stack_workspace_size(w, h, n, q, x.dtype)
+    if workspace is None:
+        workspace = _workspace(need, x.device)
+    _check_workspace(workspace, need)
+    flags = (FHT_FLAG_SHIFTED if shifted else 0) | (FHT_FLAG_MAX if op == "max" else 0)
+    _check_device(x=x, out=out, workspace=workspace)
+    rc = lib().fht_forward_stack(x.data_ptr(), it, w, h, max(x.stride(1), w), x.stride(0), n, out.data_ptr(), at,
+                                 max(out.stride(1), cols), out.stride(0), q, flags, workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(), _stream())
+    _check(rc, "fht_forward_stack")
     return out
 
 

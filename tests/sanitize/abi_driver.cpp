@@ -53,6 +53,19 @@ int main()
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 299, p, FHT_F32, c, FHT_FULL, 0, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c - 1, FHT_FULL, 0, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_FULL, 64, p, 1u << 30, nullptr) < 0);
+    {
+        size_t sb = 0;
+        EXPECT(fht_forward_stack_workspace_size(300, 200, FHT_FULL, FHT_F32, FHT_F32, 5, &sb) == FHT_OK && sb > 0);
+        EXPECT(fht_forward_stack_workspace_size(300, 200, FHT_FULL, FHT_F32, FHT_F32, 0, &sb) < 0);
+        EXPECT(fht_forward_stack(p, FHT_F32, 300, 200, 300, 300 * 200, 0, p, FHT_F32, c, r * c, FHT_FULL, 0, p, sb,
+                                 nullptr) < 0);
+        EXPECT(fht_forward_stack(p, FHT_F32, 300, 200, 300, 300 * 200 - 1, 5, p, FHT_F32, c, r * c, FHT_FULL, 0, p,
+                                 sb, nullptr) < 0);
+        EXPECT(fht_forward_stack(p, FHT_F32, 300, 200, 300, 300 * 200, 5, p, FHT_F32, c, r * c - 1, FHT_FULL, 0, p,
+                                 sb, nullptr) < 0);
+        EXPECT(fht_forward_stack(p, FHT_F32, 300, 200, 300, 300 * 200, 5, p, FHT_F32, c, r * c, FHT_FULL, 0, p,
+                                 sb - 1, nullptr) < 0);
+    }
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_Q1, FHT_FLAG_SHIFTED, p, 1u << 30, nullptr) < 0);
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_FULL, 0, p, 16, nullptr) == FHT_ERR_WORKSPACE);
     EXPECT(fht_forward(p, FHT_F32, 300, 200, 300, p, FHT_F32, c, FHT_FULL, 0, (char*)p + 4, 1u << 30, nullptr) < 0);

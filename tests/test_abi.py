@@ -5,6 +5,7 @@ import os
 import re
 
 import pytest
+import torch
 
 from paper_1811_06378_amd import fht
 
@@ -62,6 +63,41 @@ def test_adjoint_stack_sizes_and_validation():
     assert call(istr=300 * 200 - 1) == fht.FHT_ERR_INVALID
     assert call(t=fht.FHT_U8) == fht.FHT_ERR_INVALID
     assert call(ld=cols - 1) == fht.FHT_ERR_INVALID
+
+
+def test_forward_stack_sizes_and_validation():
+    L = fht.lib()
+    one = (fht.workspace_size(300, 200, "full", torch.uint8) + 255) // 256 * 256
+    assert fht.forward_stack_workspace_size(300, 200, 1, "full", torch.uint8) == one
+    assert fht.forward_stack_workspace_size(300, 200, 50, "full", torch.uint8) == 50 * one
+    # groups keep their bands within 8 GiB: 8192^2 float32 images run 3 at a time
+    big = (fht.workspace_size(8192, 8192) + 255) // 256 * 256
+    per_group = (8 << 30) // big
+    assert 1 <= per_group < 8
+    assert fht.forward_stack_workspace_size(8192, 8192, 8) == per_group * big
+    rows, cols = fht.hough_shape(300, 200)
+    p = ctypes.c_void_p(1 << 20)
+    args = dict(it=fht.FHT_U8, at=fht.FHT_I32, ldi=300, istr=300 * 200, n=3, ldh=cols, hstr=rows * cols,
+                ws=1 << 40, wsp=p, flags=0, q=15)
+
+    def call(**kw):
+        a = {**args, **kw}
+        return L.fht_forward_stack(p, a["it"], 300, 200, a["ldi"], a["istr"], a["n"], p, a["at"], a["ldh"], a["hstr"],
+                                   a["q"], a["flags"], a["wsp"], a["ws"], None)
+    assert call(n=0) == fht.FHT_ERR_INVALID
+    assert call(istr=300 * 200 - 1) == fht.FHT_ERR_INVALID
+    assert call(hstr=rows * cols - 1) == fht.FHT_ERR_INVALID
+    assert call(ldi=299) == fht.FHT_ERR_INVALID
+    assert call(ldh=cols - 1) == fht.FHT_ERR_INVALID
+    assert call(at=fht.FHT_F32) == fht.FHT_ERR_INVALID
+    assert call(flags=1, q=1) == fht.FHT_ERR_INVALID  # fhtshift needs the full image
+    assert call(ws=3 * one - 1) == fht.FHT_ERR_WORKSPACE
+    assert call(wsp=None) == fht.FHT_ERR_WORKSPACE
+    assert call(wsp=ctypes.c_void_p((1 << 20) + 64)) == fht.FHT_ERR_INVALID
+    assert L.fht_forward_stack(None, fht.FHT_U8, 300, 200, 300, 60000, 3, p, fht.FHT_I32, cols, rows * cols, 15, 0,
+                               p, 1 << 40, None) == fht.FHT_ERR_INVALID
+    with pytest.raises(ValueError):
+        fht.forward_stack_workspace_size(300, 200, 0)
 
 
 def test_timing_filter_and_empty_report_need_no_gpu():
