@@ -22,11 +22,13 @@
 namespace fht {
 
 constexpr size_t kBatchBandBudget = size_t(8) << 30;  // bytes of bands per chunk
+constexpr int64_t kBatchMapItems = int64_t(1) << 26;   // item -> group map entries (256 MB) at most
 
 struct BatchLaunch {
     int first_group;  // index into the table
     int n_groups;
     int n_items;
+    int64_t map_off;  // tile launches: the launch's item -> group map in the plan's map; -1: none
     int G;
     int rows;         // tile height of the class (64 or 32)
     bool first, last;
@@ -73,6 +75,7 @@ struct fht_batch_plan {
     std::vector<fht::BatchLaunch> launches;  // in stream order (chunks, passes, classes)
     fht::EngineGroup* d_tmpl = nullptr;
     fht::BatchTemplate* d_rel = nullptr;
+    int* d_map = nullptr;  // item -> group (relative to the launch's first group) of every tile launch
 };
 
 using namespace fht;
@@ -203,6 +206,26 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
     }
     P->n_groups = (int)tmpl.size();
     P->table_bytes = (tmpl.size() * sizeof(EngineGroup) + 255) / 256 * 256;
+    // item -> group maps of the tile launches (one load per workgroup instead
+    // of a search of the group prefix), unless they would be too large
+    std::vector<int32_t> map;
+    {
+        int64_t total = 0;
+        for (const BatchLaunch& L : P->launches)
+            if (L.G > 2) total += L.n_items;
+        for (BatchLaunch& L : P->launches) L.map_off = -1;
+        if (total <= kBatchMapItems) {
+            map.reserve((size_t)total);
+            for (BatchLaunch& L : P->launches) {
+                if (L.G <= 2) continue;
+                L.map_off = (int64_t)map.size();
+                for (int g = 0; g < L.n_groups; ++g) {
+                    const EngineGroup& e = tmpl[(size_t)L.first_group + g];
+                    for (int k = 0; k < e.count; ++k) map.push_back(g);
+                }
+            }
+        }
+    }
     // workspace: resolved table, then the bands of the largest chunk
     for (auto& e : tmpl) (void)e;
     for (BatchTemplate& r : rel) {
@@ -216,9 +239,13 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
     if (e == hipSuccess)
         e = hipMemcpy(P->d_tmpl, tmpl.data(), tmpl.size() * sizeof(EngineGroup), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(P->d_rel, rel.data(), rel.size() * sizeof(BatchTemplate), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !map.empty()) e = hipMalloc((void**)&P->d_map, map.size() * sizeof(int32_t));
+    if (e == hipSuccess && !map.empty())
+        e = hipMemcpy(P->d_map, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(P->d_tmpl);
         hipFree(P->d_rel);
+        hipFree(P->d_map);
         delete P;
         return hip_fail(e, "batch plan tables");
     }
@@ -249,7 +276,8 @@ static int batch_run(const fht_batch_plan* P, const void* const* imgs, const voi
         if (L.G <= 2)  // quadrants of at most 4 rows: one thread per Hough cell
             e = launch_table_direct(table + L.first_group, L.n_groups, L.n_items, ti, P->acc_t, s);
         else
-            e = launch_table(table + L.first_group, L.n_groups, L.n_items, L.G, L.first, L.last, L.rows,
+            e = launch_table(table + L.first_group, L.n_groups, L.n_items,
+                             L.map_off >= 0 ? P->d_map + L.map_off : nullptr, L.G, L.first, L.last, L.rows,
                              L.first ? ti : P->acc_t, P->acc_t, s);
         if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }
@@ -285,6 +313,7 @@ int fht_batch_plan_destroy(fht_batch_plan* P)
     if (dev != P->device) hipSetDevice(P->device);
     hipFree(P->d_tmpl);
     hipFree(P->d_rel);
+    hipFree(P->d_map);
     if (dev != P->device) hipSetDevice(dev);
     delete P;
     return FHT_OK;

@@ -782,19 +782,25 @@ __global__ __launch_bounds__(NW * 64, 4) void fht_pass_kernel(const PassLaunch L
 }
 
 // Many passes (of many images) of one kind in one launch: block -> item ->
-// group through the groups' first_item prefix, as in the engine queue.
+// group through the plan's item -> group map (one load), or without a map
+// through a search of the groups' first_item prefix, as in the engine queue.
 template <typename TIn, typename T, int GB, bool FIRST, bool LAST, int NW>
 __global__ __launch_bounds__(NW * 64, 4) void fht_table_kernel(const EngineGroup* __restrict__ table, int n_groups,
-                                                                int n_items)
+                                                                int n_items, const int* __restrict__ group_of)
 {
     __shared__ T lds[NW * 4 * kLdsRow];
     const int item = xcd_tile(blockIdx.x, n_items);
     if (item >= n_items) return;
-    int lo = 0, hi = n_groups - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (table[mid].first_item <= item) lo = mid;
-        else hi = mid - 1;
+    int lo = 0;
+    if (group_of) {
+        lo = group_of[item];
+    } else {
+        int hi = n_groups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (table[mid].first_item <= item) lo = mid;
+            else hi = mid - 1;
+        }
     }
     // a private copy of the descriptor: read once, its fields stay in
     // registers (the table is global memory, which every store could alias)

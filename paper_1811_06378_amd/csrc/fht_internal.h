@@ -137,9 +137,11 @@ inline size_t engine_sync_bytes(int n_groups) { return ((size_t)(n_groups + 2) *
 hipError_t launch_pass(const PassLaunch& L, int in_t, int acc_t, hipStream_t s, int op = 0);
 hipError_t launch_direct(const PassLaunch& L, int k, int in_t, int acc_t, hipStream_t s, int op = 0);
 hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc_t, hipStream_t s);
-// table: device array of n_groups groups of one kind (same G, first/last)
-hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int rows,
-                        int in_t, int acc_t, hipStream_t s);
+// table: device array of n_groups groups of one kind (same G, first/last);
+// group_of: each item's group index (device, n_items entries) or nullptr
+// (the kernel then searches the groups' first_item prefix)
+hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, const int* group_of, int G, bool first,
+                        bool last, int rows, int in_t, int acc_t, hipStream_t s);
 // direct quadrants (n <= 4) of a batch: n x W cells per group
 hipError_t launch_table_direct(const EngineGroup* table, int n_groups, int n_items, int in_t, int acc_t,
                                hipStream_t s);

@@ -75,37 +75,41 @@ hipError_t launch_engine_g(const EngineArgs& A, int grid, hipStream_t s)
 }
 
 template <typename TIn, typename T, int GB, int NW>
-hipError_t launch_table_g(const EngineGroup* table, int n_groups, int n_items, bool first, bool last, hipStream_t s)
+hipError_t launch_table_g(const EngineGroup* table, int n_groups, int n_items, const int* group_of, bool first,
+                          bool last, hipStream_t s)
 {
     const dim3 grid((n_items + kXcds - 1) / kXcds * kXcds), block(NW * 64);
     if (first && last)
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, true, NW>), grid, block, 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, true, NW>), grid, block, 0, s, table, n_groups, n_items,
+                           group_of);
     else if (first)
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, false, NW>), grid, block, 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, true, false, NW>), grid, block, 0, s, table, n_groups, n_items,
+                           group_of);
     else if (last)
-        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, true, NW>), grid, block, 0, s, table, n_groups, n_items);
+        hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, true, NW>), grid, block, 0, s, table, n_groups, n_items,
+                           group_of);
     else
         hipLaunchKernelGGL((fht_table_kernel<TIn, T, GB, false, false, NW>), grid, block, 0, s, table, n_groups,
-                           n_items);
+                           n_items, group_of);
     return hipGetLastError();
 }
 
 template <typename TIn, typename T>
-hipError_t launch_table_t(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int rows,
-                          hipStream_t s)
+hipError_t launch_table_t(const EngineGroup* table, int n_groups, int n_items, const int* group_of, int G, bool first,
+                          bool last, int rows, hipStream_t s)
 {
     const bool narrow = rows == kNarrowRows;
     switch (G) {
     case 3:
-        return narrow ? launch_table_g<TIn, T, 0, 4>(table, n_groups, n_items, first, last, s)
-                      : launch_table_g<TIn, T, 0, 8>(table, n_groups, n_items, first, last, s);
+        return narrow ? launch_table_g<TIn, T, 0, 4>(table, n_groups, n_items, group_of, first, last, s)
+                      : launch_table_g<TIn, T, 0, 8>(table, n_groups, n_items, group_of, first, last, s);
     case 4:
-        return narrow ? launch_table_g<TIn, T, 1, 4>(table, n_groups, n_items, first, last, s)
-                      : launch_table_g<TIn, T, 1, 8>(table, n_groups, n_items, first, last, s);
+        return narrow ? launch_table_g<TIn, T, 1, 4>(table, n_groups, n_items, group_of, first, last, s)
+                      : launch_table_g<TIn, T, 1, 8>(table, n_groups, n_items, group_of, first, last, s);
     case 5:
-        return narrow ? launch_table_g<TIn, T, 2, 4>(table, n_groups, n_items, first, last, s)
-                      : launch_table_g<TIn, T, 2, 8>(table, n_groups, n_items, first, last, s);
-    case 6: return narrow ? hipErrorInvalidValue : launch_table_g<TIn, T, 3, 8>(table, n_groups, n_items, first, last, s);
+        return narrow ? launch_table_g<TIn, T, 2, 4>(table, n_groups, n_items, group_of, first, last, s)
+                      : launch_table_g<TIn, T, 2, 8>(table, n_groups, n_items, group_of, first, last, s);
+    case 6: return narrow ? hipErrorInvalidValue : launch_table_g<TIn, T, 3, 8>(table, n_groups, n_items, group_of, first, last, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -261,8 +265,8 @@ hipError_t launch_adj_direct_t(const AdjLaunch& L, int k, hipStream_t s)
     hipError_t launch_direct_max_##name(const PassLaunch& L, int k, hipStream_t s); \
     hipError_t launch_engine_##name(const EngineArgs& A, int G, int grid, hipStream_t s); \
     hipError_t launch_direct_##name(const PassLaunch& L, int k, hipStream_t s);                 \
-    hipError_t launch_table_##name(const EngineGroup* table, int n_groups, int n_items, int G, bool first, \
-                                   bool last, int rows, hipStream_t s);                                  \
+    hipError_t launch_table_##name(const EngineGroup* table, int n_groups, int n_items, const int* group_of, int G, \
+                                   bool first, bool last, int rows, hipStream_t s);                      \
     hipError_t launch_table_direct_##name(const EngineGroup* table, int n_groups, int n_items, hipStream_t s);
 FHT_DECLARE_FWD(u8)
 FHT_DECLARE_FWD(i32)

@@ -59,22 +59,22 @@ hipError_t launch_engine(const EngineArgs& A, int G, int grid, int in_t, int acc
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_table_typed(const EngineGroup* table, int n_groups, int n_items, int G, bool first,
-                                     bool last, int rows, int in_t, int acc_t, hipStream_t s)
+static hipError_t launch_table_typed(const EngineGroup* table, int n_groups, int n_items, const int* group_of,
+                                     int G, bool first, bool last, int rows, int in_t, int acc_t, hipStream_t s)
 {
-    if (in_t == 0 && acc_t == 1) return launch_table_u8(table, n_groups, n_items, G, first, last, rows, s);
-    if (in_t == 1 && acc_t == 1) return launch_table_i32(table, n_groups, n_items, G, first, last, rows, s);
-    if (in_t == 2 && acc_t == 2) return launch_table_f32(table, n_groups, n_items, G, first, last, rows, s);
+    if (in_t == 0 && acc_t == 1) return launch_table_u8(table, n_groups, n_items, group_of, G, first, last, rows, s);
+    if (in_t == 1 && acc_t == 1) return launch_table_i32(table, n_groups, n_items, group_of, G, first, last, rows, s);
+    if (in_t == 2 && acc_t == 2) return launch_table_f32(table, n_groups, n_items, group_of, G, first, last, rows, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, int G, bool first, bool last, int rows,
-                        int in_t, int acc_t, hipStream_t s)
+hipError_t launch_table(const EngineGroup* table, int n_groups, int n_items, const int* group_of, int G, bool first,
+                        bool last, int rows, int in_t, int acc_t, hipStream_t s)
 {
     int slot = -1;
     if (timing_on())
         slot = timing_begin(kernel_name("fht_table_kernel", in_t, acc_t, G - 3, first, last, -1, rows / 8), s);
-    const hipError_t e = launch_table_typed(table, n_groups, n_items, G, first, last, rows, in_t, acc_t, s);
+    const hipError_t e = launch_table_typed(table, n_groups, n_items, group_of, G, first, last, rows, in_t, acc_t, s);
     timing_end(slot, s);
     return e;
 }
