@@ -275,7 +275,9 @@ int fht_range_adjoint(const void* grad, int t, int64_t ld_grad, int S1, int S, i
  *   one thread per Hough cell inside the same plan.  FHT_ERR_UNSUPPORTED if
  *   one launch class of one chunk would exceed 2^31 work items.  Allocates
  *   the plan's device tables (the only allocating entry point) on the
- *   current device.  *ws_bytes receives the
+ *   current device; with up to 2^26 tile items they include an item ->
+ *   group map (environment FHT_BATCH_MAP=0 at plan creation leaves it out:
+ *   the kernels then search the group table).  *ws_bytes receives the
  *   workspace size, *out_elems the total number of output elements;
  *   out_offsets (host, n entries, may be NULL) receives each image's element
  *   offset in the packed output (each image's Hough image is stored densely,

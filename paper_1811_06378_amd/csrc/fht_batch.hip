@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -214,7 +215,10 @@ int fht_batch_plan_create(const int32_t* ws, const int32_t* hs, int n, unsigned 
         for (const BatchLaunch& L : P->launches)
             if (L.G > 2) total += L.n_items;
         for (BatchLaunch& L : P->launches) L.map_off = -1;
-        if (total <= kBatchMapItems) {
+        // FHT_BATCH_MAP=0 in the environment keeps the search (tests of it)
+        const char* env = getenv("FHT_BATCH_MAP");
+        const bool use_map = !(env && env[0] == '0');
+        if (use_map && total <= kBatchMapItems) {
             map.reserve((size_t)total);
             for (BatchLaunch& L : P->launches) {
                 if (L.G <= 2) continue;

@@ -1,6 +1,7 @@
-"""The opt-in launch variant (read once per process from the environment):
-FHT_ENGINE=1, the persistent queue engine.  It runs in a child process that
-checks a few forward transforms against the oracle and prints OK."""
+"""Launch variants read once per process from the environment, each run in
+a child process that checks transforms against the oracle and prints OK:
+FHT_ENGINE=1, the opt-in persistent queue engine; FHT_BATCH_MAP=0, batch
+plans without their item -> group map."""
 import os
 import subprocess
 import sys
@@ -75,3 +76,31 @@ def test_engine_reports_expired_waits():
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
     assert r.returncode == 0 and r.stdout.strip().endswith("TIMEOUT REPORTED"), (r.returncode, r.stdout[-2000:],
                                                                                    r.stderr[-2000:])
+
+
+# Batch plans without the item -> group map (FHT_BATCH_MAP=0): the table
+# kernels search the group prefix instead; a mixed batch stays bit-exact.
+MAPLESS_CHILD = r"""
+import sys
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+import numpy as np, torch
+import oracle
+from paper_1811_06378_amd import fht, synth
+sizes = [(5, 5), (13, 40), (64, 64), (100, 37), (129, 257), (520, 300), (2, 100), (1000, 9)]
+for kind, dt in (("u8", torch.uint8), ("f32", torch.float32)):
+    imgs = [synth.random_image(h, w, kind, seed=40 + i) for i, (h, w) in enumerate(sizes)]
+    plan = fht.BatchPlan(sizes, in_dtype=dt)
+    outs = plan([torch.from_numpy(a).cuda() for a in imgs])
+    torch.cuda.synchronize()
+    for a, got in zip(imgs, outs):
+        want = oracle.full(a.astype(np.float64), single=(kind == "f32"))
+        assert np.array_equal(got.cpu().numpy().astype(np.float64), want), (kind, a.shape)
+print("OK")
+"""
+
+
+def test_batch_plan_without_group_map():
+    code = MAPLESS_CHILD.format(root=ROOT, tests=os.path.join(ROOT, "tests"))
+    env = {**os.environ, "FHT_BATCH_MAP": "0"}
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and r.stdout.strip().endswith("OK"), (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
