@@ -1511,17 +1511,34 @@ template <typename T>
 __global__ __launch_bounds__(256) void fht_shift_kernel(const T* in, int64_t ld_in, T* out, int64_t ld_out,
                                                         int hp, int wp, int inverse)
 {
+    static_assert(sizeof(T) == 4, "4-byte cells");
+    typedef unsigned u32x4u __attribute__((ext_vector_type(4), aligned(4)));
     const int W = hp + wp;
     const int rows = 2 * (hp + wp) - 3;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= W) return;
+    // four consecutive output cells per thread
+    const int x0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (x0 >= W) return;
     // grid y is capped (65535); rows beyond it are taken in strides
     for (int r = blockIdx.y; r < rows; r += gridDim.y) {
         int roll = row_roll(r, hp, wp) % W;
         if (inverse) roll = (W - roll) % W;
-        int src = x - roll;
+        int src = x0 - roll;
         if (src < 0) src += W;
-        out[(long long)r * ld_out + x] = in[(long long)r * ld_in + src];
+        const T* pin = in + (long long)r * ld_in;
+        T* po = out + (long long)r * ld_out + x0;
+        if (x0 + 4 <= W && src + 4 <= W) {
+            // the four source cells are consecutive: one 16-byte load and
+            // store (dword alignment suffices on gfx950)
+            *reinterpret_cast<u32x4u*>(po) = *reinterpret_cast<const u32x4u*>(pin + src);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (x0 + c >= W) break;
+                int s = src + c;
+                if (s >= W) s -= W;
+                po[c] = pin[s];
+            }
+        }
     }
 }
 

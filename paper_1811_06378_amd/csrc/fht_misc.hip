@@ -192,7 +192,7 @@ hipError_t launch_shift(const void* in, int64_t ld_in, void* out, int64_t ld_out
         hipLaunchKernelGGL(fht_shift_inplace_kernel<uint32_t>, dim3(rows), dim3(1024), lds_bytes, s,
                            (uint32_t*)out, ld_out, hp, wp, inverse);
     } else {
-        hipLaunchKernelGGL(fht_shift_kernel<uint32_t>, dim3((W + 255) / 256, rows < 65535 ? rows : 65535), dim3(256), 0, s,
+        hipLaunchKernelGGL(fht_shift_kernel<uint32_t>, dim3((W + 1023) / 1024, rows < 65535 ? rows : 65535), dim3(256), 0, s,
                            (const uint32_t*)in, ld_in, (uint32_t*)out, ld_out, hp, wp, inverse);
     }
     return hipGetLastError();

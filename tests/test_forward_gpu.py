@@ -64,7 +64,7 @@ def test_full_shifted(h, w, kind):
     assert_equal(got.astype(np.float64), want, "shifted %s" % kind)
 
 
-@pytest.mark.parametrize("h,w", [(2, 2), (8, 8), (13, 5), (128, 64), (300, 520)])
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 2), (4, 1), (2, 2), (8, 8), (13, 5), (3, 17), (128, 64), (300, 520)])
 @pytest.mark.parametrize("inplace", [False, True])
 def test_shift_kernel(h, w, inplace):
     img = _img(h, w, "i32", seed=6)
