@@ -103,11 +103,11 @@ def test_batch_adjoint_subsets_shifted_and_strides(quads, shifted):
     assert bool(torch.all(out_big[:, h:, :] == -1.0)) and bool(torch.all(out_big[:, :, w:] == -1.0))
 
 
-def test_batch_adjoint_tiny_quadrants():
-    # sides below 8: direct kernels inside the stack
-    h, w = 3, 6
+@pytest.mark.parametrize("h,w", [(3, 6), (1, 1), (2, 9), (4, 4), (1, 40), (40, 2)])
+def test_batch_adjoint_tiny_quadrants(h, w):
+    # sides up to 4: direct kernels inside the stack (the image index on the grid)
     rows, cols = fht.hough_shape(w, h)
-    g = dev(np.random.default_rng(3).standard_normal((5, rows, cols)).astype(np.float32))
+    g = dev(np.random.default_rng(3 + h * w).standard_normal((5, rows, cols)).astype(np.float32))
     got = P.batch_adjoint(g, w, h)
     for i in range(5):
         assert torch.equal(got[i], P.adjoint(g[i], w, h))
