@@ -385,6 +385,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--fwd-only", action="store_true", help="time only the forward (profiling runs)")
+    ap.add_argument("--fwd-adjoint-only", action="store_true",
+                    help="time only the forward and the forward + adjoint step (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -520,6 +522,7 @@ def main():
         del g, gimg
         log("fwd+adjoint %.3f ms" % ms_fa)
 
+    if not args.fwd_only and not args.fwd_adjoint_only:
         imgs8 = [x] + [torch.from_numpy(synth.dense4096(s, size=side)).cuda() for s in range(1, 8)]
         x8 = torch.stack(imgs8)
         result["batched"] = bench_stack(fht, torch, x8, max(1, args.steps // 4), 1, "batched 8x4096^2 f32")
